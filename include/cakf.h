@@ -1,0 +1,171 @@
+/*
+ * cakf.h - C ABI of the MI355X computation-aware Kalman filter library (libcakf.so).
+ *
+ * The library runs the update step of the computation-aware Kalman filter (CAKF) and
+ * its smoother (CAKS) of Pfoertner, Wenger, Cockayne and Hennig (arXiv 2405.08971)
+ * for the separable spatiotemporal prior with an Ornstein-Uhlenbeck temporal factor
+ * (Lemma C.1 with D' = 1):
+ *
+ *   state   u_k in R^n at the n spatial points X,
+ *   prior   Sigma = signal_var * K(X, X)        (Matern(nu) spatial correlation K),
+ *   dynamics u_k = a u_{k-1} + q_k,  q_k ~ N(0, (1 - a^2) Sigma),  a = exp(-dt / ell_t),
+ *   observations y_k = u_k[idx_k] + eps_k,  eps_k ~ N(0, noise_var I).
+ *
+ * Covariances are never formed.  The filter state is a mean m (n) and a downdate
+ * factor M (n x rank) with covariance Sigma - M M^T (Prop. A.2).  Kernel matrices are
+ * evaluated tile by tile inside the kernels and never stored.
+ *
+ * Conventions for every entry point:
+ *  - All device buffers hold FP32 unless stated; "device" means GPU memory of the
+ *    device current at cakf_create.  Matrices are row-major unless stated.
+ *  - Work is enqueued asynchronously on the configured stream; no entry point
+ *    synchronises the host except cakf_diagnostics and cakf_loglik, which say so.
+ *  - Argument errors are detected on the host and returned as negative codes before
+ *    anything is enqueued.  Numerical events (a dropped action, a non-finite value)
+ *    are never errors: they are counted in a device status word (cakf_diagnostics).
+ *  - A context is not thread-safe.  Results are deterministic: the same inputs give
+ *    bitwise identical outputs (no floating-point atomics are used).
+ */
+#ifndef CAKF_H
+#define CAKF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cakf_ctx cakf_ctx;
+
+/* Status codes. */
+#define CAKF_OK        0
+#define CAKF_E_ARG    -1   /* invalid argument (null pointer, size out of range)      */
+#define CAKF_E_HIP    -2   /* a HIP runtime call failed                                */
+#define CAKF_E_NOMEM  -3   /* device allocation failed in cakf_create                  */
+#define CAKF_E_STATE  -4   /* call out of order (e.g. truncate with nothing to drop)   */
+#define CAKF_E_SOLVER -5   /* rocBLAS / rocSOLVER returned an error                    */
+
+/* Spatial Matern kernel, identified by 2*nu. */
+#define CAKF_MATERN12 1
+#define CAKF_MATERN32 3
+#define CAKF_MATERN52 5
+
+/* Distance between points: Euclidean (chordal for points on the unit sphere, the
+ * extrinsic construction of App. D.2.3) or great-circle (arccos of the dot product of
+ * unit vectors). */
+#define CAKF_DIST_EUCLID   0
+#define CAKF_DIST_GEODESIC 1
+
+/* Arithmetic of the kernel-matrix x block product P^- H^T [W w] (Alg. 2):
+ *  FP32   - FP32 kernel tiles, FP32 contraction;
+ *  BF16   - FP32 kernel tiles rounded to BF16, BF16 MFMA with FP32 accumulation;
+ *  BF16X3 - BF16 MFMA on split operands: K = Kh + Kl, B = Bh + Bl (each part BF16),
+ *           Y = Kh Bh + Kl Bh + Kh Bl, which restores close to FP32 accuracy.
+ * The observation-space loop (actions, Gram matrix) always runs in FP32 with FP64
+ * small matrices. */
+#define CAKF_PREC_FP32   0
+#define CAKF_PREC_BF16   1
+#define CAKF_PREC_BF16X3 2
+
+/* Policy (Sec. 3.3): CG - the current residual is the next action (App. E, the
+ * policy of all the paper's experiments); GIVEN - the actions are supplied by the
+ * caller (any full-rank S is admissible). */
+#define CAKF_POLICY_CG    0
+#define CAKF_POLICY_GIVEN 1
+
+typedef struct {
+    int n;                  /* spatial points = state dimension, >= 1                */
+    int dim;                /* coordinates per point: 2 or 3                         */
+    const float* X;         /* device, n x dim row-major; read once in cakf_create   */
+    int kernel;             /* CAKF_MATERN12/32/52                                   */
+    int dist;               /* CAKF_DIST_*; GEODESIC needs dim = 3 unit vectors      */
+    double lengthscale;     /* spatial lengthscale ell > 0                           */
+    double signal_var;      /* sigma_f^2 > 0                                         */
+    double noise_var;       /* observation noise variance > 0                        */
+    double ou_coeff;        /* a = exp(-dt / ell_t), 0 < a <= 1                      */
+    int max_obs;            /* largest m passed to cakf_update                       */
+    int max_actions;        /* action budget i per update, 1..256 (at most m used)   */
+    int max_rank;           /* rank cap r of the truncated factor, 1..1024           */
+    int policy;             /* CAKF_POLICY_*                                         */
+    double resid_tol;       /* stop when ||r|| <= resid_tol * ||r0||; 0 = never     */
+    double pivot_tol;       /* drop action j when its Ghat-orthogonal part keeps no
+                               more than pivot_tol of s_j^T Ghat s_j (breakdown);
+                               typical 1e-10                                         */
+    int prec;               /* CAKF_PREC_* of the block product                      */
+    void* stream;           /* hipStream_t for all work; NULL = the null stream      */
+} cakf_config;
+
+/* Optional per-update record, all caller-owned device buffers; any field may be NULL.
+ * Sizes use m of the update and i = max_actions; entries beyond the number of kept
+ * actions are zero. */
+typedef struct {
+    float*   S;             /* m x i: the actions used (Ghat-unnormalised residuals
+                               for CG, the given columns for GIVEN)                  */
+    float*   W_obs;         /* m x i: S L^{-T}, i.e. V of the iterative update in
+                               observation coordinates (W = H^T W_obs)              */
+    float*   w_obs;         /* m: S (S^T Ghat S)^{-1} S^T r0 (w = H^T w_obs)         */
+    double*  chol;          /* i x i: lower Cholesky factor L of S^T Ghat S          */
+    double*  loglik;        /* 1: projected log-likelihood term of this step         */
+    int*     n_actions;     /* 1: number of actions kept                             */
+} cakf_record;
+
+/* Create a context: copies and pre-scales X, allocates every workspace and the filter
+ * state (mean = 0, rank = 0, i.e. the prior N(0, Sigma)).  No later call allocates. */
+int cakf_create(const cakf_config* cfg, cakf_ctx** out);
+
+/* Release a context and all its device memory (synchronises its stream). */
+void cakf_destroy(cakf_ctx* ctx);
+
+/* Reset the filter state to the prior (mean 0, empty factor). */
+int cakf_reset(cakf_ctx* ctx);
+
+/* Device views of the context-owned filter state: mean (n), factor (n x rank,
+ * row-major with leading dimension *ld).  The pointers stay valid until the next
+ * cakf_update / cakf_truncate / cakf_step / cakf_set_state / cakf_destroy.  Any output
+ * pointer may be NULL. */
+int cakf_state(cakf_ctx* ctx, float** mean, float** factor, int* ld, int* rank);
+
+/* Copy the state out into caller-owned device buffers: mean (n) and factor (n x rank,
+ * leading dimension ld >= rank).  Either pointer may be NULL. */
+int cakf_copy_state(cakf_ctx* ctx, float* mean, float* factor, int ld);
+
+/* Copy a state in (device buffers: mean n, factor n x rank with leading dimension ld).
+ * rank <= max_rank. */
+int cakf_set_state(cakf_ctx* ctx, const float* mean, const float* factor, int ld, int rank);
+
+/* Predict (Alg. 1): m <- a m, M <- a M. */
+int cakf_predict(cakf_ctx* ctx);
+
+/* Update (Alg. 2 / the iterative update of App. B) with m observations y (device, m)
+ * at the distinct state indices idx (device int32, m, each in [0, n)).
+ * actions: device m x i row-major, required for POLICY_GIVEN, ignored for CG.
+ * Afterwards the factor has rank + max_actions columns (the untruncated M_k; columns
+ * of dropped actions are zero).  m == 0 means no data (the IsMissing branch). */
+int cakf_update(cakf_ctx* ctx, const int32_t* idx, const float* y, int m,
+                const float* actions, const cakf_record* rec);
+
+/* Truncate (Sec. 3.2): replace M by M V_r, where V_r holds the leading
+ * min(max_rank, rank) eigenvectors of M^T M (FP64 Gram and FP64 eigensolver), so that
+ * M M^T keeps its best rank-r approximation.  rotation (device FP64, rank x r_new,
+ * row-major, nullable) receives V_r.  A factor of at most max_rank columns is left
+ * unchanged. */
+int cakf_truncate(cakf_ctx* ctx, double* rotation);
+
+/* One filter step of Alg. 1: predict, update (skipped when m == 0), truncate. */
+int cakf_step(cakf_ctx* ctx, const int32_t* idx, const float* y, int m,
+              const float* actions, const cakf_record* rec);
+
+/* Marginal variances diag(Sigma - M M^T) of the current state at the state indices
+ * rows (device int32, count entries; NULL = all n) into out (device, count).  A row
+ * index outside [0, n) yields NaN. */
+int cakf_marginal_var(cakf_ctx* ctx, const int32_t* rows, int count, float* out);
+
+/* Device status words since the last reset: actions dropped on breakdown, non-finite
+ * pivots, and observation indices outside [0, n) (each read as index 0).  Any output
+ * pointer may be NULL.  Synchronises the stream. */
+int cakf_diagnostics(cakf_ctx* ctx, int* dropped_actions, int* nonfinite, int* bad_index);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAKF_H */

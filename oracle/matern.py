@@ -10,7 +10,9 @@ out the standard half-integer closed forms with u = d / ell:
 
 and their derivatives with respect to the lengthscale.  Distances are Euclidean (for
 points on the unit sphere this is the chordal/extrinsic distance of App. D.2.3) or
-great-circle (arccos of the inner product of unit vectors).
+great-circle: the angle between the two position vectors, atan2(|a x b|, <a, b>),
+which equals arccos(<a, b>) for unit vectors and stays exact when the inputs carry
+rounding in their length.
 
 Test infrastructure only; not part of the product path.
 """
@@ -30,7 +32,11 @@ def distances(A: np.ndarray, B: np.ndarray, dist: int = EUCLID) -> np.ndarray:
         diff = A[:, None, :] - B[None, :, :]
         return np.sqrt(np.sum(diff * diff, axis=-1))
     if dist == GEODESIC:
-        return np.arccos(np.clip(A @ B.T, -1.0, 1.0))
+        ax, ay, az = (A[:, k][:, None] for k in range(3))
+        bx, by, bz = (B[:, k][None, :] for k in range(3))
+        cross = np.sqrt((ay * bz - az * by) ** 2 + (az * bx - ax * bz) ** 2
+                        + (ax * by - ay * bx) ** 2)
+        return np.arctan2(cross, A @ B.T)
     raise ValueError("unknown distance")
 
 

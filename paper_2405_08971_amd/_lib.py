@@ -1,0 +1,160 @@
+"""ctypes binding of libcakf.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (include/cakf.h) and
+passes device pointers of torch tensors through unchanged; no arithmetic happens here.
+The library must have been built (paper_2405_08971_amd/build.py); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcakf.so")
+
+CAKF_OK, CAKF_E_ARG, CAKF_E_HIP, CAKF_E_NOMEM, CAKF_E_STATE, CAKF_E_SOLVER = 0, -1, -2, -3, -4, -5
+MATERN = {1: 1, 3: 3, 5: 5}
+DIST = {"euclid": 0, "geodesic": 1}
+PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+POLICY = {"cg": 0, "given": 1}
+_ERR = {CAKF_E_ARG: "invalid argument", CAKF_E_HIP: "HIP runtime error",
+        CAKF_E_NOMEM: "device allocation failed", CAKF_E_STATE: "call out of order",
+        CAKF_E_SOLVER: "rocBLAS/rocSOLVER error"}
+
+
+class cakf_config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int), ("dim", ctypes.c_int), ("X", ctypes.c_void_p),
+        ("kernel", ctypes.c_int), ("dist", ctypes.c_int),
+        ("lengthscale", ctypes.c_double), ("signal_var", ctypes.c_double),
+        ("noise_var", ctypes.c_double), ("ou_coeff", ctypes.c_double),
+        ("max_obs", ctypes.c_int), ("max_actions", ctypes.c_int), ("max_rank", ctypes.c_int),
+        ("policy", ctypes.c_int), ("resid_tol", ctypes.c_double),
+        ("pivot_tol", ctypes.c_double), ("prec", ctypes.c_int), ("stream", ctypes.c_void_p),
+    ]
+
+
+class cakf_record(ctypes.Structure):
+    _fields_ = [
+        ("S", ctypes.c_void_p), ("W_obs", ctypes.c_void_p), ("w_obs", ctypes.c_void_p),
+        ("chol", ctypes.c_void_p), ("loglik", ctypes.c_void_p), ("n_actions", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcakf.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2405_08971_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        sigs = {
+            "cakf_create": (i, [ctypes.POINTER(cakf_config), ctypes.POINTER(vp)]),
+            "cakf_destroy": (None, [vp]),
+            "cakf_reset": (i, [vp]),
+            "cakf_state": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                               ctypes.POINTER(i), ctypes.POINTER(i)]),
+            "cakf_copy_state": (i, [vp, vp, vp, i]),
+            "cakf_set_state": (i, [vp, vp, vp, i, i]),
+            "cakf_predict": (i, [vp]),
+            "cakf_update": (i, [vp, vp, vp, i, vp, ctypes.POINTER(cakf_record)]),
+            "cakf_truncate": (i, [vp, vp]),
+            "cakf_step": (i, [vp, vp, vp, i, vp, ctypes.POINTER(cakf_record)]),
+            "cakf_marginal_var": (i, [vp, vp, i, vp]),
+            "cakf_diagnostics": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i),
+                                     ctypes.POINTER(i)]),
+        }
+        for name, (res, args) in sigs.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str) -> None:
+    if rc != CAKF_OK:
+        raise RuntimeError(f"{what} failed: {_ERR.get(rc, rc)} ({rc})")
+
+
+def ptr(t) -> int:
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libcakf takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libcakf takes contiguous tensors")
+    return t.data_ptr()
+
+
+def stream_handle(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+# --- one wrapper per entry point ------------------------------------------------------
+def cakf_create(cfg: cakf_config) -> int:
+    h = ctypes.c_void_p()
+    check(lib().cakf_create(ctypes.byref(cfg), ctypes.byref(h)), "cakf_create")
+    return h.value
+
+
+def cakf_destroy(ctx: int) -> None:
+    lib().cakf_destroy(ctx)
+
+
+def cakf_reset(ctx: int) -> None:
+    check(lib().cakf_reset(ctx), "cakf_reset")
+
+
+def cakf_state(ctx: int):
+    mean, factor = ctypes.c_void_p(), ctypes.c_void_p()
+    ld, rank = ctypes.c_int(), ctypes.c_int()
+    check(lib().cakf_state(ctx, ctypes.byref(mean), ctypes.byref(factor), ctypes.byref(ld),
+                           ctypes.byref(rank)), "cakf_state")
+    return mean.value, factor.value, ld.value, rank.value
+
+
+def cakf_copy_state(ctx: int, mean, factor, ld: int) -> None:
+    check(lib().cakf_copy_state(ctx, ptr(mean), ptr(factor), ld), "cakf_copy_state")
+
+
+def cakf_set_state(ctx: int, mean, factor, ld: int, rank: int) -> None:
+    check(lib().cakf_set_state(ctx, ptr(mean), ptr(factor), ld, rank), "cakf_set_state")
+
+
+def cakf_predict(ctx: int) -> None:
+    check(lib().cakf_predict(ctx), "cakf_predict")
+
+
+def cakf_update(ctx: int, idx, y, m: int, actions=None, rec: cakf_record = None) -> None:
+    check(lib().cakf_update(ctx, ptr(idx), ptr(y), m, ptr(actions),
+                            ctypes.byref(rec) if rec is not None else None), "cakf_update")
+
+
+def cakf_truncate(ctx: int, rotation=None) -> None:
+    check(lib().cakf_truncate(ctx, ptr(rotation)), "cakf_truncate")
+
+
+def cakf_step(ctx: int, idx, y, m: int, actions=None, rec: cakf_record = None) -> None:
+    check(lib().cakf_step(ctx, ptr(idx), ptr(y), m, ptr(actions),
+                          ctypes.byref(rec) if rec is not None else None), "cakf_step")
+
+
+def cakf_marginal_var(ctx: int, rows, count: int, out) -> None:
+    check(lib().cakf_marginal_var(ctx, ptr(rows), count, ptr(out)), "cakf_marginal_var")
+
+
+def cakf_diagnostics(ctx: int):
+    dr, nf, bi = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib().cakf_diagnostics(ctx, ctypes.byref(dr), ctypes.byref(nf), ctypes.byref(bi)),
+          "cakf_diagnostics")
+    return dr.value, nf.value, bi.value

@@ -1,0 +1,416 @@
+// C ABI of libcakf: context management and the orchestration of one filter step
+// (Alg. 1: predict, update, truncate) on one HIP stream.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/cakf.h"
+#include "cakf_common.h"
+#include "launchers.h"
+
+using namespace cakf;
+
+namespace {
+
+inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+struct Diag {
+    int dropped;
+    int nonfinite;
+    int bad_index;
+};
+
+}  // namespace
+
+struct cakf_ctx {
+    cakf_config cfg;
+    hipStream_t stream;
+    rocblas_handle blas;
+    int device;
+    // dimensions
+    int n, r, imax, mmax, mpmax, ldM, bp, Kmax;
+    size_t gram_work_elems;
+    // state
+    float* mean;
+    float* M[2];
+    int cur;          // index of the buffer holding the factor
+    int rank;
+    // observation space workspace
+    float4* Xs;
+    float4* Xo;
+    float* r0;
+    float* Mo;
+    float* S;
+    float* U;
+    float* T;
+    float* part;
+    double* gpart;
+    double* ttpart;
+    float* mpart;
+    double *Linv, *L, *LSinv, *alpha, *beta;
+    LoopState* ls;
+    Diag* diag;
+    // block product
+    float* B;
+    float* Q;
+    // truncation
+    double* G;
+    double* gwork;
+    double* eigval;
+    double* offdiag;
+    int* info;
+    float* Vr;
+    void* blas_ws;
+};
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        if ((x) != hipSuccess) return CAKF_E_HIP;    \
+    } while (0)
+#define BLAS_TRY(x)                                          \
+    do {                                                     \
+        if ((x) != rocblas_status_success) return CAKF_E_SOLVER; \
+    } while (0)
+
+static void free_all(cakf_ctx* c) {
+    void* ptrs[] = {c->mean, c->M[0], c->M[1], c->Xs, c->Xo, c->r0, c->Mo, c->S, c->U, c->T,
+                    c->part, c->gpart, c->ttpart, c->mpart, c->Linv, c->L, c->LSinv,
+                    c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->G, c->gwork, c->eigval,
+                    c->offdiag, c->info, c->Vr, c->blas_ws};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+template <typename Tp>
+static int dalloc(Tp** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)p, count * sizeof(Tp)) != hipSuccess) {
+        *p = nullptr;
+        return CAKF_E_NOMEM;
+    }
+    return CAKF_OK;
+}
+
+static int validate(const cakf_config* c) {
+    if (!c || !c->X) return CAKF_E_ARG;
+    if (c->n < 1 || (c->dim != 2 && c->dim != 3)) return CAKF_E_ARG;
+    if (c->kernel != CAKF_MATERN12 && c->kernel != CAKF_MATERN32 && c->kernel != CAKF_MATERN52)
+        return CAKF_E_ARG;
+    if (c->dist != CAKF_DIST_EUCLID && c->dist != CAKF_DIST_GEODESIC) return CAKF_E_ARG;
+    if (c->dist == CAKF_DIST_GEODESIC && c->dim != 3) return CAKF_E_ARG;
+    if (!(c->lengthscale > 0) || !(c->signal_var > 0) || !(c->noise_var > 0)) return CAKF_E_ARG;
+    if (!(c->ou_coeff > 0) || c->ou_coeff > 1) return CAKF_E_ARG;
+    if (c->max_obs < 1 || c->max_actions < 1 || c->max_actions > 256) return CAKF_E_ARG;
+    if (c->max_rank < 1 || c->max_rank > 1024) return CAKF_E_ARG;
+    if (c->policy != CAKF_POLICY_CG && c->policy != CAKF_POLICY_GIVEN) return CAKF_E_ARG;
+    if (c->prec != CAKF_PREC_FP32 && c->prec != CAKF_PREC_BF16 && c->prec != CAKF_PREC_BF16X3)
+        return CAKF_E_ARG;
+    if (c->resid_tol < 0 || c->pivot_tol < 0) return CAKF_E_ARG;
+    return CAKF_OK;
+}
+
+extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
+    if (!out) return CAKF_E_ARG;
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    cakf_ctx* c = new (std::nothrow) cakf_ctx;
+    if (!c) return CAKF_E_NOMEM;
+    std::memset(c, 0, sizeof(*c));
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)cfg->stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return CAKF_E_HIP;
+    }
+    c->n = cfg->n;
+    c->r = cfg->max_rank;
+    c->imax = cfg->max_actions;
+    c->mmax = cfg->max_obs;
+    c->mpmax = round_up(c->mmax, SYM_TILE);
+    c->ldM = round_up(c->r + c->imax + 1, 4);
+    c->bp = round_up(c->imax + 1, 32);
+    c->Kmax = c->r + c->imax;
+    c->gram_work_elems = (size_t)16 * c->Kmax * c->Kmax;
+    const size_t n = c->n;
+    const int nbmax = c->mpmax / SYM_TILE;
+    const int nblk = (c->mmax + 255) / 256;
+    const int ntt = (c->r + 255) / 256;
+    rc = CAKF_OK;
+    rc |= dalloc(&c->mean, n);
+    rc |= dalloc(&c->M[0], n * c->ldM);
+    rc |= dalloc(&c->M[1], n * c->ldM);
+    rc |= dalloc(&c->Xs, n);
+    rc |= dalloc(&c->Xo, c->mpmax);
+    rc |= dalloc(&c->r0, c->mpmax);
+    rc |= dalloc(&c->Mo, (size_t)c->mpmax * c->r);
+    rc |= dalloc(&c->S, (size_t)c->mpmax * c->imax);
+    rc |= dalloc(&c->U, (size_t)c->mpmax * c->imax);
+    rc |= dalloc(&c->T, (size_t)c->r * c->imax);
+    rc |= dalloc(&c->part, (size_t)nbmax * c->mpmax);
+    rc |= dalloc(&c->gpart, (size_t)nblk * (2 * c->imax + 1));
+    rc |= dalloc(&c->ttpart, (size_t)ntt * c->imax);
+    rc |= dalloc(&c->mpart, (size_t)nblk * c->r);
+    rc |= dalloc(&c->Linv, (size_t)c->imax * c->imax);
+    rc |= dalloc(&c->L, (size_t)c->imax * c->imax);
+    rc |= dalloc(&c->LSinv, (size_t)c->imax * c->imax);
+    rc |= dalloc(&c->alpha, c->imax);
+    rc |= dalloc(&c->beta, c->imax);
+    rc |= dalloc(&c->ls, 1);
+    rc |= dalloc(&c->diag, 1);
+    rc |= dalloc(&c->B, (size_t)c->mpmax * c->bp);
+    rc |= dalloc(&c->Q, (size_t)c->r * c->bp);
+    rc |= dalloc(&c->G, (size_t)c->Kmax * c->Kmax);
+    rc |= dalloc(&c->gwork, c->gram_work_elems);
+    rc |= dalloc(&c->eigval, c->Kmax);
+    rc |= dalloc(&c->offdiag, c->Kmax);
+    rc |= dalloc(&c->info, 1);
+    rc |= dalloc(&c->Vr, (size_t)c->Kmax * c->r);
+    if (rc) {
+        free_all(c);
+        delete c;
+        return CAKF_E_NOMEM;
+    }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        free_all(c);
+        delete c;
+        return CAKF_E_SOLVER;
+    }
+    rocblas_set_stream(c->blas, c->stream);
+    rocblas_set_atomics_mode(c->blas, rocblas_atomics_not_allowed);
+    rocblas_set_pointer_mode(c->blas, rocblas_pointer_mode_host);
+    // Size the library workspace once (largest eigenproblem) so no later call allocates.
+    size_t ws = 0;
+    rocblas_start_device_memory_size_query(c->blas);
+    rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, c->Kmax, c->G,
+                     c->Kmax, c->eigval, c->offdiag, c->info);
+    rocblas_stop_device_memory_size_query(c->blas, &ws);
+    ws = std::max<size_t>(ws, 1 << 20);
+    if (hipMalloc(&c->blas_ws, ws) != hipSuccess ||
+        rocblas_set_workspace(c->blas, c->blas_ws, ws) != rocblas_status_success) {
+        rocblas_destroy_handle(c->blas);
+        free_all(c);
+        delete c;
+        return CAKF_E_NOMEM;
+    }
+    // Pre-scaled points and the prior state.
+    const int nu2 = cfg->kernel;
+    const double scale = std::sqrt((double)nu2) / cfg->lengthscale;
+    launch_prescale(cfg->X, c->n, cfg->dim, (float)scale, cfg->dist, c->Xs, c->stream);
+    if (hipMemsetAsync(c->mean, 0, n * sizeof(float), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        rocblas_destroy_handle(c->blas);
+        free_all(c);
+        delete c;
+        return CAKF_E_HIP;
+    }
+    c->cur = 0;
+    c->rank = 0;
+    *out = c;
+    return CAKF_OK;
+}
+
+extern "C" void cakf_destroy(cakf_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    rocblas_destroy_handle(c->blas);
+    free_all(c);
+    delete c;
+}
+
+extern "C" int cakf_reset(cakf_ctx* c) {
+    if (!c) return CAKF_E_ARG;
+    HIP_TRY(hipMemsetAsync(c->mean, 0, (size_t)c->n * sizeof(float), c->stream));
+    HIP_TRY(hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream));
+    c->rank = 0;
+    return CAKF_OK;
+}
+
+extern "C" int cakf_state(cakf_ctx* c, float** mean, float** factor, int* ld, int* rank) {
+    if (!c) return CAKF_E_ARG;
+    if (mean) *mean = c->mean;
+    if (factor) *factor = c->M[c->cur];
+    if (ld) *ld = c->ldM;
+    if (rank) *rank = c->rank;
+    return CAKF_OK;
+}
+
+extern "C" int cakf_copy_state(cakf_ctx* c, float* mean, float* factor, int ld) {
+    if (!c || (factor && ld < c->rank)) return CAKF_E_ARG;
+    if (mean)
+        HIP_TRY(hipMemcpyAsync(mean, c->mean, (size_t)c->n * sizeof(float),
+                               hipMemcpyDeviceToDevice, c->stream));
+    if (factor && c->rank > 0)
+        launch_copy_rows(c->M[c->cur], c->ldM, factor, ld, c->n, c->rank, c->stream);
+    return CAKF_OK;
+}
+
+extern "C" int cakf_set_state(cakf_ctx* c, const float* mean, const float* factor, int ld,
+                              int rank) {
+    if (!c || !mean || rank < 0 || rank > c->r || (rank > 0 && (!factor || ld < rank)))
+        return CAKF_E_ARG;
+    HIP_TRY(hipMemcpyAsync(c->mean, mean, (size_t)c->n * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+    if (rank > 0) launch_copy_rows(factor, ld, c->M[c->cur], c->ldM, c->n, rank, c->stream);
+    c->rank = rank;
+    return CAKF_OK;
+}
+
+extern "C" int cakf_predict(cakf_ctx* c) {
+    if (!c) return CAKF_E_ARG;
+    const float a = (float)c->cfg.ou_coeff;
+    if (a != 1.0f) launch_scale_state(c->mean, c->M[c->cur], c->n, c->ldM, c->rank, a, c->stream);
+    return CAKF_OK;
+}
+
+// Fill the scalar record fields of a step without data.
+__global__ void k_empty_record(double* loglik, int* n_actions) {
+    if (loglik) *loglik = 0.0;
+    if (n_actions) *n_actions = 0;
+}
+
+__global__ void k_count_diag(const LoopState* ls, Diag* dg) {
+    dg->dropped += ls->dropped;
+    dg->nonfinite += ls->nonfinite;
+    dg->bad_index += ls->bad_index;
+}
+
+extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int m,
+                           const float* actions, const cakf_record* rec) {
+    if (!c || m < 0 || m > c->mmax) return CAKF_E_ARG;
+    const cakf_record none = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (!rec) rec = &none;
+    hipStream_t st = c->stream;
+    if (m == 0) {
+        hipLaunchKernelGGL(k_empty_record, dim3(1), dim3(1), 0, st, rec->loglik, rec->n_actions);
+        return CAKF_OK;
+    }
+    if (!idx || !y) return CAKF_E_ARG;
+    const bool cg = c->cfg.policy == CAKF_POLICY_CG;
+    if (!cg && !actions) return CAKF_E_ARG;
+    if (c->rank > c->r) return CAKF_E_STATE;
+    const int imax = std::min(c->imax, m);
+    ObsDims d;
+    d.m = m;
+    d.mp = round_up(m, SYM_TILE);
+    d.imax = c->imax;
+    d.rank = c->rank;
+    d.ldmo = c->r;
+    float* M = c->M[c->cur];
+    const size_t tri = (size_t)c->imax * c->imax * sizeof(double);
+    HIP_TRY(hipMemsetAsync(c->ls, 0, sizeof(LoopState), st));
+    HIP_TRY(hipMemsetAsync(c->Linv, 0, tri, st));
+    HIP_TRY(hipMemsetAsync(c->L, 0, tri, st));
+    HIP_TRY(hipMemsetAsync(c->LSinv, 0, tri, st));
+    HIP_TRY(hipMemsetAsync(c->alpha, 0, c->imax * sizeof(double), st));
+    HIP_TRY(hipMemsetAsync(c->beta, 0, c->imax * sizeof(double), st));
+    launch_gather(c->Xs, c->n, c->mean, M, c->ldM, idx, y, actions, cg ? 1 : 0, d, c->Xo, c->r0,
+                  c->Mo, c->S, c->U, c->ls, st);
+    if (d.rank > 0) {
+        if (cg) {
+            int nb = 0;
+            launch_colsum_partial(c->Mo, c->r, m, d.rank, c->r0, 1, c->mpart, c->r, st, &nb);
+            launch_colsum_final(c->mpart, c->r, nb, d.rank, c->T, c->imax, st);
+        } else {
+            // T^T = S^T Mo  (imax x rank, column-major ld imax) = row-major T (rank x imax)
+            const float one = 1.0f, zero = 0.0f;
+            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
+                                   c->imax, d.rank, m, &one, c->S, c->imax, c->Mo, c->r, &zero,
+                                   c->T, c->imax));
+        }
+    }
+    const int nu2 = c->cfg.kernel, dist = c->cfg.dist;
+    int nmpart = 0;
+    for (int j = 0; j < imax; ++j) {
+        launch_sym_tiles(nu2, dist, c->Xo, c->S, d, j, c->part,
+                         (cg && j > 0) ? c->mpart : nullptr, nmpart, c->T, c->ttpart, c->ls, st);
+        int nb2 = 0;
+        launch_form_u(c->part, c->S, c->U, c->r0, d, j, c->cfg.signal_var, c->gpart, c->ls, st,
+                      &nb2);
+        launch_tail(c->gpart, nb2, c->ttpart, d, j, c->cfg.noise_var, c->cfg.resid_tol,
+                    c->cfg.pivot_tol, c->Linv, c->L, c->LSinv, c->alpha, c->beta, c->ls, st);
+        if (cg && j + 1 < imax)
+            launch_next_action(c->U, c->Mo, c->r0, c->S, c->beta, c->T,
+                               (float)c->cfg.noise_var, d, j, c->mpart, c->ls, st, &nmpart);
+    }
+    launch_build_block(c->S, c->Linv, c->beta, d, c->B, c->bp, c->bp, rec->W_obs, rec->w_obs,
+                       rec->S, c->ls, st);
+    const int b = c->imax + 1;
+    if (d.rank > 0) {
+        const float one = 1.0f, zero = 0.0f;
+        // Q = Mo^T B  (rank x b, column-major ld r)
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
+                               d.rank, b, m, &one, c->Mo, c->r, c->B, c->bp, &zero, c->Q, c->r));
+    }
+    // Y = Sigma[:, idx] B into the new columns rank .. rank + b of the factor
+    launch_block_product(nu2, dist, c->cfg.prec, c->Xs, c->n, c->Xo, m, c->B, c->bp, b,
+                         (float)c->cfg.signal_var, M + d.rank, c->ldM, st);
+    if (d.rank > 0) {
+        const float mone = -1.0f, one = 1.0f;
+        // Y -= M^- Q  (the low-rank part of P^- H^T [W w])
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, b,
+                               c->n, d.rank, &mone, c->Q, c->r, M, c->ldM, &one, M + d.rank,
+                               c->ldM));
+    }
+    launch_mean_add(c->mean, M, c->n, c->ldM, d.rank + c->imax, st);
+    launch_finish_record(c->ls, c->L, c->imax, rec->chol, rec->loglik, rec->n_actions, st);
+    hipLaunchKernelGGL(k_count_diag, dim3(1), dim3(1), 0, st, c->ls, c->diag);
+    c->rank += c->imax;
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
+    if (!c) return CAKF_E_ARG;
+    const int K = c->rank;
+    if (K <= c->r) return CAKF_OK;
+    hipStream_t st = c->stream;
+    float* M = c->M[c->cur];
+    float* Mn = c->M[1 - c->cur];
+    launch_gram64(M, c->n, c->ldM, K, c->G, c->gwork, c->gram_work_elems, st);
+    BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K, c->G, K,
+                              c->eigval, c->offdiag, c->info));
+    launch_pick_rotation(c->G, K, c->r, c->Vr, rotation, st);
+    const float one = 1.0f, zero = 0.0f;
+    // M_new (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n)
+    BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, c->r,
+                           c->n, K, &one, c->Vr, K, M, c->ldM, &zero, Mn, c->ldM));
+    c->cur = 1 - c->cur;
+    c->rank = c->r;
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+extern "C" int cakf_step(cakf_ctx* c, const int32_t* idx, const float* y, int m,
+                         const float* actions, const cakf_record* rec) {
+    int rc = cakf_predict(c);
+    if (rc) return rc;
+    rc = cakf_update(c, idx, y, m, actions, rec);
+    if (rc) return rc;
+    return cakf_truncate(c, nullptr);
+}
+
+extern "C" int cakf_marginal_var(cakf_ctx* c, const int32_t* rows, int count, float* out) {
+    if (!c || !out || count < 0) return CAKF_E_ARG;
+    if (!rows && count != c->n) return CAKF_E_ARG;
+    if (count == 0) return CAKF_OK;
+    launch_marginal_var(c->M[c->cur], c->n, c->ldM, c->rank, (float)c->cfg.signal_var, rows,
+                        count, out, c->stream);
+    return CAKF_OK;
+}
+
+extern "C" int cakf_diagnostics(cakf_ctx* c, int* dropped, int* nonfinite, int* bad_index) {
+    if (!c) return CAKF_E_ARG;
+    Diag h;
+    HIP_TRY(hipMemcpyAsync(&h, c->diag, sizeof(Diag), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (dropped) *dropped = h.dropped;
+    if (nonfinite) *nonfinite = h.nonfinite;
+    if (bad_index) *bad_index = h.bad_index;
+    return CAKF_OK;
+}

@@ -1,0 +1,85 @@
+// Host-side launchers of the libcakf kernels (one translation unit per kernel group).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cakf {
+
+constexpr int SYM_TILE = 128;       // side of the symmetric kernel tiles of the action loop
+constexpr int ROWS_PER_WAVE = 64;   // observation rows per wave in the row kernels
+
+// Device-resident scalars of one update's action loop.
+struct LoopState {
+    int stop;          // set once the loop has stopped (budget, tolerance or breakdown)
+    int i_eff;         // actions kept so far
+    int dropped;       // actions dropped on breakdown since the last reset
+    int nonfinite;     // non-finite pivots since the last reset
+    double logdet_c;   // log det S^T Ghat S of the kept actions
+    double logdet_s;   // log det S^T S of the kept actions
+    double alpha2;     // ||L^{-1} S^T r0||^2
+    double q00;        // ||s_0||^2 (CG: ||r0||^2)
+    double loglik;     // projected log-likelihood term of the kept actions
+    int bad_index;     // observation indices outside [0, n) seen by the gather
+};
+
+// Shapes shared by the observation-space kernels.
+struct ObsDims {
+    int m;        // observations
+    int mp;       // m rounded up to SYM_TILE
+    int imax;     // action budget; leading dimension of S, U, T and the FP64 triangles
+    int rank;     // columns of the predictive factor
+    int ldmo;     // leading dimension of Mo (= max_rank)
+};
+
+// ---- misc.hip
+void launch_prescale(const float* X, int n, int dim, float c, int dist, float4* Xs,
+                     hipStream_t st);
+void launch_scale_state(float* mean, float* M, int n, int ld, int rank, float a, hipStream_t st);
+void launch_mean_add(float* mean, const float* M, int n, int ld, int col, hipStream_t st);
+void launch_marginal_var(const float* M, int n, int ld, int rank, float sigma_f2,
+                         const int32_t* rows, int count, float* out, hipStream_t st);
+void launch_copy_rows(const float* src, int lds, float* dst, int ldd, int rows, int cols,
+                      hipStream_t st);
+
+// ---- obs_loop.hip
+void launch_gather(const float4* Xs, int n, const float* mean, const float* M, int ldM,
+                   const int32_t* idx, const float* y, const float* given, int cg,
+                   const ObsDims& d, float4* Xo, float* r0, float* Mo, float* S, float* U,
+                   LoopState* ls, hipStream_t st);
+void launch_colsum_partial(const float* A, int lda, int rows, int cols, const float* x,
+                           int ldx, float* partial, int ldp, hipStream_t st, int* nblk_out);
+void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, float* out,
+                         int ldo, hipStream_t st);
+void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
+                      int j, float* part, const float* mpart, int nmpart, float* T,
+                      double* ttpart, const LoopState* ls, hipStream_t st);
+void launch_form_u(const float* part, const float* S, float* U, const float* r0,
+                   const ObsDims& d, int j, double sigma_f2, double* gpart,
+                   const LoopState* ls, hipStream_t st, int* nblk_out);
+void launch_tail(const double* gpart, int nblk, const double* ttpart, const ObsDims& d,
+                 int j, double noise_var, double resid_tol, double pivot_tol, double* Linv,
+                 double* L, double* LSinv, double* alpha, double* beta, LoopState* ls,
+                 hipStream_t st);
+void launch_next_action(const float* U, const float* Mo, const float* r0, float* S,
+                        const double* beta, const float* T, float noise_var,
+                        const ObsDims& d, int j, float* mpart, const LoopState* ls,
+                        hipStream_t st, int* nblk_out);
+void launch_build_block(const float* S, const double* Linv, const double* beta,
+                        const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
+                        float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st);
+void launch_finish_record(const LoopState* ls, const double* L, int imax, double* rec_chol,
+                          double* rec_loglik, int* rec_n, hipStream_t st);
+
+// ---- block_product.hip
+void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
+                          const float4* Xo, int m, const float* B, int ldb, int bcols,
+                          float sigma_f2, float* out, int ldo, hipStream_t st);
+
+// ---- truncate.hip
+void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* work,
+                   size_t work_elems, hipStream_t st);
+void launch_pick_rotation(const double* E, int K, int r, float* Vr, double* rot_out,
+                          hipStream_t st);
+
+}  // namespace cakf

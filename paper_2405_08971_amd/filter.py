@@ -1,0 +1,117 @@
+"""Convenience wrapper over the libcakf C ABI for torch device tensors.
+
+Only argument marshalling and buffer allocation happen here; every step of the filter
+runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+import torch
+
+from . import _lib as L
+
+
+class Record:
+    """Caller-owned device buffers for one update's record (see cakf_record)."""
+
+    def __init__(self, m: int, i: int, device="cuda"):
+        self.m, self.i = m, i
+        self.S = torch.zeros((m, i), dtype=torch.float32, device=device)
+        self.W_obs = torch.zeros((m, i), dtype=torch.float32, device=device)
+        self.w_obs = torch.zeros((m,), dtype=torch.float32, device=device)
+        self.chol = torch.zeros((i, i), dtype=torch.float64, device=device)
+        self.loglik = torch.zeros((1,), dtype=torch.float64, device=device)
+        self.n_actions = torch.zeros((1,), dtype=torch.int32, device=device)
+
+    def c(self) -> L.cakf_record:
+        return L.cakf_record(L.ptr(self.S), L.ptr(self.W_obs), L.ptr(self.w_obs),
+                             L.ptr(self.chol), L.ptr(self.loglik), L.ptr(self.n_actions))
+
+
+class CAKF:
+    """One filter context (state + workspace) on the current device and stream."""
+
+    def __init__(self, X: torch.Tensor, *, nu2: int = 3, dist: str = "euclid",
+                 lengthscale: float, signal_var: float = 1.0, noise_var: float,
+                 ou_coeff: float, max_obs: int, max_actions: int, max_rank: int,
+                 policy: str = "cg", resid_tol: float = 0.0, pivot_tol: float = 1e-10,
+                 prec: str = "fp32", stream: Optional[torch.cuda.Stream] = None):
+        if X.dtype != torch.float32 or X.dim() != 2:
+            raise ValueError("X must be a float32 (n, dim) device tensor")
+        X = X.contiguous()
+        self.n, self.dim = X.shape
+        self.max_actions, self.max_rank, self.max_obs = max_actions, max_rank, max_obs
+        self.signal_var = signal_var
+        self.policy = policy
+        cfg = L.cakf_config(
+            n=self.n, dim=self.dim, X=L.ptr(X), kernel=L.MATERN[nu2], dist=L.DIST[dist],
+            lengthscale=lengthscale, signal_var=signal_var, noise_var=noise_var,
+            ou_coeff=ou_coeff, max_obs=max_obs, max_actions=max_actions, max_rank=max_rank,
+            policy=L.POLICY[policy], resid_tol=resid_tol, pivot_tol=pivot_tol,
+            prec=L.PREC[prec], stream=L.stream_handle(stream))
+        self._X = X
+        self.ctx = L.cakf_create(cfg)
+
+    # -- lifecycle -------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.cakf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        L.cakf_reset(self.ctx)
+
+    # -- filter ----------------------------------------------------------------------
+    def predict(self):
+        L.cakf_predict(self.ctx)
+
+    def update(self, idx: Optional[torch.Tensor], y: Optional[torch.Tensor],
+               actions: Optional[torch.Tensor] = None, record: Optional[Record] = None):
+        m = 0 if idx is None else int(idx.numel())
+        rec = record.c() if record is not None else None
+        L.cakf_update(self.ctx, idx, y, m, actions, rec)
+
+    def truncate(self, rotation: Optional[torch.Tensor] = None):
+        L.cakf_truncate(self.ctx, rotation)
+
+    def step(self, idx, y, actions=None, record: Optional[Record] = None):
+        m = 0 if idx is None else int(idx.numel())
+        rec = record.c() if record is not None else None
+        L.cakf_step(self.ctx, idx, y, m, actions, rec)
+
+    # -- state -----------------------------------------------------------------------
+    @property
+    def rank(self) -> int:
+        return L.cakf_state(self.ctx)[3]
+
+    def state(self):
+        """(mean, factor) copies: float32 (n,) and (n, rank)."""
+        rank = self.rank
+        mean = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        factor = torch.empty((self.n, max(rank, 1)), dtype=torch.float32, device="cuda")
+        L.cakf_copy_state(self.ctx, mean, factor, factor.shape[1])
+        return mean, factor[:, :rank]
+
+    def set_state(self, mean: torch.Tensor, factor: torch.Tensor):
+        factor = factor.contiguous()
+        rank = factor.shape[1]
+        L.cakf_set_state(self.ctx, mean.contiguous(), factor if rank else None,
+                         max(rank, 1), rank)
+
+    def marginal_var(self, rows: Optional[torch.Tensor] = None) -> torch.Tensor:
+        count = self.n if rows is None else int(rows.numel())
+        out = torch.empty(count, dtype=torch.float32, device="cuda")
+        L.cakf_marginal_var(self.ctx, rows, count, out)
+        return out
+
+    def diagnostics(self):
+        return L.cakf_diagnostics(self.ctx)

@@ -1,0 +1,115 @@
+"""Helpers shared by the GPU tests: run the HIP library and the FP64 oracle on the same
+seeded inputs and compare.  (Not a test module.)"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle.cakf import Model, run_filter
+from paper_2405_08971_amd.workload import Config, Workload
+
+
+def rel_mean_err(x, ref) -> float:
+    """mean |x - ref| / mean |ref| (the per-result relative error)."""
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = np.mean(np.abs(ref))
+    return float(np.mean(np.abs(x - ref)) / (den if den > 0 else 1.0))
+
+
+def small_config(name="p", **kw) -> Config:
+    base = dict(name=name, n=800, dim=3, nu2=3, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
+                T=6, m=300, noise_var=0.05, i=8, r=20)
+    base.update(kw)
+    return Config(**base)
+
+
+def inputs(cfg: Config, seed=0, missing_steps=(), policy="given"):
+    """float32-rounded inputs shared by both sides."""
+    wl = Workload(cfg, seed=seed, n_features=512)
+    X = wl.X.astype(np.float32)
+    steps, actions = [], []
+    for k in range(1, cfg.T + 1):
+        if k in missing_steps:
+            steps.append(None)
+            actions.append(None)
+            continue
+        idx, y = wl.step(k)
+        steps.append((idx.astype(np.int32), y.astype(np.float32)))
+        actions.append(wl.actions(k).astype(np.float32) if policy == "given" else None)
+    return X, steps, actions
+
+
+def oracle_run(cfg: Config, X, steps, actions, policy, pivot_tol=1e-10, resid_tol=0.0):
+    model = Model(X.astype(np.float64), cfg.nu2, cfg.ell, cfg.sigma_f2, cfg.a, cfg.noise_var,
+                  cfg.dist)
+    st = [None if s is None else (s[0].astype(np.int64), s[1].astype(np.float64)) for s in steps]
+    acts = None if policy != "given" else [None if a is None else a.astype(np.float64)
+                                           for a in actions]
+    return model, run_filter(model, st, cfg.i, cfg.r, policy=policy, actions=acts,
+                             pivot_tol=pivot_tol, resid_tol=resid_tol)
+
+
+def gpu_run(cfg: Config, X, steps, actions, policy, prec="fp32", probes=None,
+            pivot_tol=1e-10, resid_tol=0.0):
+    """Run the library step by step; returns per-step host results."""
+    import torch
+    from paper_2405_08971_amd.filter import CAKF, Record
+
+    dev = "cuda"
+    Xd = torch.from_numpy(X).to(dev)
+    f = CAKF(Xd, nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid",
+             lengthscale=cfg.ell, signal_var=cfg.sigma_f2, noise_var=cfg.noise_var,
+             ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy=policy,
+             pivot_tol=pivot_tol, resid_tol=resid_tol, prec=prec)
+    P = None if probes is None else torch.from_numpy(probes.astype(np.float32)).to(dev)
+    out = []
+    for k, item in enumerate(steps):
+        f.predict()
+        rec = None
+        if item is None:
+            f.update(None, None)
+        else:
+            idx = torch.from_numpy(item[0]).to(dev)
+            y = torch.from_numpy(item[1]).to(dev)
+            a = None if actions[k] is None else torch.from_numpy(actions[k]).to(dev)
+            rec = Record(len(item[0]), cfg.i)
+            f.update(idx, y, a, rec)
+        mean, M = f.state()
+        var = f.marginal_var()
+        res = dict(mean=mean.cpu().numpy().astype(np.float64),
+                   var=var.cpu().numpy().astype(np.float64), rank=M.shape[1])
+        if P is not None:
+            res["MMt_probe"] = (M.double() @ (M.double().T @ P.double())).cpu().numpy()
+        if rec is not None:
+            torch.cuda.synchronize()
+            res.update(loglik=float(rec.loglik.item()), n_actions=int(rec.n_actions.item()),
+                       S=rec.S.cpu().numpy(), W_obs=rec.W_obs.cpu().numpy(),
+                       w_obs=rec.w_obs.cpu().numpy())
+        else:
+            res.update(loglik=0.0, n_actions=0)
+        f.truncate()
+        Mp = f.state()[1]
+        res["var_trunc"] = f.marginal_var().cpu().numpy().astype(np.float64)
+        res["rank_trunc"] = Mp.shape[1]
+        out.append(res)
+    torch.cuda.synchronize()
+    f.close()
+    return out
+
+
+def compare(cfg, model, recs, gpu, probes=None):
+    """Per-step relative mean errors of mean, marginal variance and log-likelihood."""
+    errs = []
+    for rec, g in zip(recs, gpu):
+        e = dict(mean=rel_mean_err(g["mean"], rec.m),
+                 var=rel_mean_err(g["var"], rec.marginal_var(cfg.sigma_f2)),
+                 var_trunc=rel_mean_err(g["var_trunc"],
+                                        cfg.sigma_f2 - np.sum(rec.M_plus ** 2, axis=1)),
+                 loglik=abs(g["loglik"] - rec.loglik) / max(abs(rec.loglik), 1e-300),
+                 n_actions=(g["n_actions"], rec.i_eff))
+        if probes is not None:
+            e["MMt"] = rel_mean_err(g["MMt_probe"], rec.M @ (rec.M.T @ probes))
+        errs.append(e)
+    return errs

@@ -35,6 +35,17 @@ def test_lengthscale_derivative_matches_finite_differences(nu2):
     np.testing.assert_allclose(matern.matern_dell(nu2, d, ell, s2), fd, rtol=1e-7, atol=1e-10)
 
 
+def test_geodesic_is_arccos_for_unit_vectors_and_zero_on_the_diagonal():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((7, 3))
+    A /= np.linalg.norm(A, axis=1, keepdims=True)
+    geo = matern.distances(A, A, matern.GEODESIC)
+    np.testing.assert_allclose(geo, np.arccos(np.clip(A @ A.T, -1, 1)), atol=1e-7)
+    # rounding of the length (e.g. FP32 inputs) must not move a point away from itself
+    A32 = A.astype(np.float32).astype(np.float64)
+    assert np.abs(np.diag(matern.distances(A32, A32, matern.GEODESIC))).max() < 1e-12
+
+
 def test_geodesic_is_twice_arcsine_of_half_chord():
     rng = np.random.default_rng(1)
     A = rng.standard_normal((9, 3))
