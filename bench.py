@@ -1,0 +1,207 @@
+#!/usr/bin/env python
+"""Throughput of the computation-aware Kalman filter step on one MI355X.
+
+A step is one pass of Alg. 1 (predict, update with CG actions, truncate) over one time
+step of the n = 65536 precision workload (Matern-5/2 on 65536 Fibonacci-sphere points,
+m = 16384 observations per step, i = 128 actions, rank cap r = 512).  All inputs are
+generated before the timed region and are resident in device memory.
+
+Prints one JSON line.  Besides the throughput it carries the roofline figures of the
+dominant kernel (the symmetric Matern tile matvec of the action loop, measured with HIP
+events on the library's stream over the timed region) and the FP64 oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("filter steps/sec at n=65536 (BF16-MFMA vs FP32 plain, ≤1e-3 err); "
+          "% MFMA peak")
+# MI355X peaks (public figures; transcendental rate: 32 lanes/clk/CU at 2.4 GHz on 256
+# CUs, i.e. half the FP32 lane rate, measured for v_exp_f32 and v_sqrt_f32).
+PEAK_TRANS = 256 * 32 * 2.4e9          # transcendental evaluations / s
+PEAK_BF16 = 2.5e15                     # dense BF16 MFMA flop / s
+PEAK_HBM = 8.0e12                      # B / s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--config", default="c3")
+    p.add_argument("--prec", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
+    p.add_argument("--no-fp32-compare", action="store_true",
+                   help="skip the FP32-plain run reported next to the headline mode")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--seed", type=int, default=0)
+    return p.parse_args()
+
+
+def device_inputs(wl, ks):
+    import torch
+    out = []
+    for k in ks:
+        idx, y = wl.step(k)
+        out.append((torch.from_numpy(idx.astype(np.int32)).cuda(),
+                    torch.from_numpy(y.astype(np.float32)).cuda()))
+    return out
+
+
+def run(cfg, X, inputs, warmup, steps, prec):
+    import torch
+    from paper_2405_08971_amd.filter import CAKF
+
+    f = CAKF(X, nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid",
+             lengthscale=cfg.ell, signal_var=cfg.sigma_f2, noise_var=cfg.noise_var,
+             ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy="cg",
+             prec=prec)
+    for k in range(warmup):
+        f.step(*inputs[k])
+    torch.cuda.synchronize()
+    f.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        f.step(*inputs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = f.profile_read()
+    f.profile(False)
+    mean, _ = f.state()
+    var = f.marginal_var()
+    dropped, nonfinite, bad = f.diagnostics()
+    f.close()
+    return dict(elapsed=elapsed, prof=prof, mean=mean.cpu().numpy(), var=var.cpu().numpy(),
+                dropped=dropped, nonfinite=nonfinite)
+
+
+def cpu_baseline(cfg, wl):
+    """The FP64 oracle on a bounded sample of one step of the same workload.
+
+    Sample: a quarter of the rows of one projected-Gram product Ghat v (the unit of the
+    action loop; the oracle's iterative update makes three per action plus one batch
+    product for the log-likelihood), the block product on 1/64 of the state rows, and
+    one truncation of an n x (r + i) factor.  Seconds per step are extrapolated as
+    (3 i + 1) * 4 t_Ghat_quarter + 64 t_block_slice + t_truncate."""
+    from oracle.cakf import Model, truncate
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    model = Model(wl.X, cfg.nu2, cfg.ell, cfg.sigma_f2, cfg.a, cfg.noise_var, cfg.dist)
+    idx, y = wl.step(1)
+    rng = np.random.default_rng(0)
+    r0 = np.asarray(y, np.float64)
+    Mo = 0.01 * rng.standard_normal((cfg.m, cfg.r))
+    q = cfg.m // 4
+    t = time.perf_counter()
+    _ = (model.cov_matmul(idx[:q], idx, r0) - Mo[:q] @ (Mo.T @ r0)
+         + cfg.noise_var * r0[:q])
+    t_ghat = (time.perf_counter() - t) * 4
+    rows = np.arange(0, cfg.n, 64)
+    B = rng.standard_normal((cfg.m, cfg.i + 1))
+    t = time.perf_counter()
+    _ = model.cov_matmul(rows, idx, B)
+    t_block = (time.perf_counter() - t) * 64
+    M = rng.standard_normal((cfg.n, cfg.r + cfg.i)).astype(np.float64)
+    t = time.perf_counter()
+    _ = truncate(M, cfg.r)
+    t_trunc = time.perf_counter() - t
+    s_per_step = (3 * cfg.i + 1) * t_ghat + t_block + t_trunc
+    return dict(value=1.0 / s_per_step, unit="steps/s", cores=threads, kind="oracle",
+                sample=(f"one step of {cfg.name}: 1/4 of a Ghat product (x4: {t_ghat:.1f} s), block "
+                        f"product on 1/64 of the rows (x64: {t_block:.1f} s), one "
+                        f"truncation ({t_trunc:.2f} s); s/step = (3i+1) t_Ghat + block + "
+                        f"truncation = {s_per_step:.0f} s; elementwise kernel evaluation "
+                        f"is single-threaded NumPy, BLAS uses {threads} threads"))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the filter "
+              "is single-device, see the design notes for how it would shard.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2405_08971_amd.workload import CONFIGS, Workload
+
+    cfg = CONFIGS[args.config]
+    wl = Workload(cfg, seed=args.seed)
+    X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
+    nsteps = args.warmup + args.steps
+    inputs = device_inputs(wl, range(1, nsteps + 1))
+    torch.cuda.synchronize()
+
+    res = run(cfg, X, inputs, args.warmup, args.steps, args.prec)
+    fp32 = None
+    if not args.no_fp32_compare and args.prec != "fp32":
+        fp32 = run(cfg, X, inputs, args.warmup, args.steps, "fp32")
+
+    m = cfg.m
+    sym_ms, sym_n = res["prof"]["sym_tiles"]
+    sym_avg = sym_ms / max(sym_n, 1) * 1e-3
+    trans_per_launch = 2.0 * m * (m + 1) / 2.0          # 2 per unique symmetric entry
+    achieved = trans_per_launch / sym_avg if sym_avg > 0 else 0.0
+    bp_ms, bp_n = res["prof"]["block_product"]
+    bp_avg = bp_ms / max(bp_n, 1) * 1e-3
+    b = cfg.i + 1
+    mfma_flop = 2.0 * cfg.n * m * b
+    line = {
+        "metric": METRIC,
+        "value": args.steps / res["elapsed"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["elapsed"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32" if args.prec == "fp32" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: n={cfg.n} Fibonacci-sphere points, "
+                               f"Matern-{cfg.nu2}/2 chordal, m={cfg.m}, i={cfg.i} CG "
+                               f"actions, r={cfg.r}",
+                   "block_product": args.prec, "action_loop": "fp32 (fp64 Gram)",
+                   "truncation": "fp64 Gram + fp64 eigensolver"},
+        "roofline": {"bound": "alu", "kernel": "sym_tiles (action-loop Matern matvec)",
+                     "achieved": achieved / 1e12, "peak": PEAK_TRANS / 1e12,
+                     "unit": "Ttrans/s", "frac": achieved / PEAK_TRANS, "traffic": None,
+                     "avg_launch_us": sym_avg * 1e6, "launches": sym_n},
+        "phases_ms_per_step": {k: v[0] / args.steps for k, v in res["prof"].items()},
+        "block_product": {"avg_launch_us": bp_avg * 1e6,
+                          "mfma_frac_algorithmic": (mfma_flop / bp_avg / PEAK_BF16)
+                          if bp_avg > 0 else None},
+        "diagnostics": {"dropped_actions": res["dropped"], "nonfinite": res["nonfinite"]},
+    }
+    if fp32 is not None:
+        line["fp32_plain"] = {
+            "value": args.steps / fp32["elapsed"],
+            "ms_per_step": fp32["elapsed"] / args.steps * 1e3,
+            "phases_ms_per_step": {k: v[0] / args.steps for k, v in fp32["prof"].items()},
+        }
+        sub = wl.subset(2048)
+        mref, vref = fp32["mean"][sub], fp32["var"][sub]
+        line["fp32_plain"]["rel_diff_vs_headline"] = {
+            "mean": float(np.mean(np.abs(res["mean"][sub] - mref)) / np.mean(np.abs(mref))),
+            "var": float(np.mean(np.abs(res["var"][sub] - vref)) / np.mean(np.abs(vref)))}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,6 +92,7 @@ typedef struct {
                                more than pivot_tol of s_j^T Ghat s_j (breakdown);
                                typical 1e-10                                         */
     int prec;               /* CAKF_PREC_* of the block product                      */
+    int smoother;           /* nonzero: also allocate the smoother workspace         */
     void* stream;           /* hipStream_t for all work; NULL = the null stream      */
 } cakf_config;
 
@@ -164,6 +165,68 @@ int cakf_marginal_var(cakf_ctx* ctx, const int32_t* rows, int count, float* out)
  * pivots, and observation indices outside [0, n) (each read as index 0).  Any output
  * pointer may be NULL.  Synchronises the stream. */
 int cakf_diagnostics(cakf_ctx* ctx, int* dropped_actions, int* nonfinite, int* bad_index);
+
+/* One backward step k of the computation-aware RTS smoother (Alg. 3).  Inputs come from
+ * the filter run (caller-owned device buffers, read only):
+ *   mean        m_k, filter mean after the update of step k (n);
+ *   factor      M_k, the untruncated filter factor after the update of step k
+ *               (n x rank, row-major, leading dimension ld);
+ *   pred_factor M_k^- = a M_{k-1}^+, the predictive factor of step k (n x pred_rank);
+ *   idx, w_obs, W_obs, m   the observation indices and the record of step k (w_obs: m,
+ *               W_obs: m x max_actions); m = 0 for a step without data.
+ * The smoother requires the m indices of a step to be distinct. */
+typedef struct {
+    const float* mean;
+    const float* factor;
+    int ld, rank;
+    const float* pred_factor;
+    int pred_ld, pred_rank;
+    const int32_t* idx;
+    const float* w_obs;
+    const float* W_obs;
+    int m;
+} cakf_smooth_input;
+
+/* Start the backward pass at the last step T (Alg. 3): ws_T = H_T^T w_obs,
+ * Ws_T = H_T^T W_obs from the record of step T (m = 0: no data).  Needs
+ * cfg.smoother != 0.  The smoothed moments of step T are the filter's. */
+int cakf_smooth_begin(cakf_ctx* ctx, const int32_t* idx, const float* w_obs,
+                      const float* W_obs, int m);
+
+/* One backward step k = T-1, ..., 1 (Alg. 3):
+ *   smoothed mean   m_k + P_k A^T ws_{k+1}                          -> mean_out (n)
+ *   smoothed factor (M_k, P_k A^T Ws_{k+1})                         -> factor_out
+ *                   (n x *out_rank, leading dimension ld_out)
+ *   marginal variances sigma_f^2 - row sums of the factor squared   -> var_out (n)
+ * then advances ws, Ws to step k (truncating Ws to max_rank columns, Sec. 3.2).  Any
+ * output may be NULL.  P_k = Sigma - M_k M_k^T uses the untruncated filter factor. */
+int cakf_smooth_step(cakf_ctx* ctx, const cakf_smooth_input* in, float* mean_out,
+                     float* factor_out, int ld_out, float* var_out, int* out_rank);
+
+/* Phases timed by the profiling hooks (HIP events on the context stream around each
+ * launch of the phase). */
+#define CAKF_PHASE_SYM_TILES     0   /* kernel-matrix x action matvec of the action loop */
+#define CAKF_PHASE_FORM_U        1   /* tile reduction and Gram partial sums             */
+#define CAKF_PHASE_TAIL          2   /* FP64 incremental Cholesky                        */
+#define CAKF_PHASE_NEXT_ACTION   3   /* CG residual = next action                        */
+#define CAKF_PHASE_BLOCK_PRODUCT 4   /* kernel-matrix x [W w] block product               */
+#define CAKF_PHASE_GRAM          5   /* FP64 Gram matrix of the factor                   */
+#define CAKF_PHASE_EIG           6   /* FP64 symmetric eigensolver                       */
+#define CAKF_PHASE_ROTATE        7   /* factor rotation M V_r                            */
+#define CAKF_PHASE_PREDICT       8   /* cakf_step: predict                               */
+#define CAKF_PHASE_UPDATE        9   /* cakf_step: update                                */
+#define CAKF_PHASE_TRUNCATE     10   /* cakf_step: truncate                              */
+#define CAKF_PHASES             11
+
+/* Enable (on != 0, resets the counters) or disable per-phase timing.  Enabling creates
+ * HIP events once (host-side objects, no device memory); at most 2048 launches per
+ * phase are timed between reads. */
+int cakf_profile_enable(cakf_ctx* ctx, int on);
+
+/* Total milliseconds and number of timed launches per phase since the last enable or
+ * read (arrays of CAKF_PHASES entries), then reset the counters.  Synchronises the
+ * stream. */
+int cakf_profile_read(cakf_ctx* ctx, double* total_ms, int* launches);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,8 @@ MATERN = {1: 1, 3: 3, 5: 5}
 DIST = {"euclid": 0, "geodesic": 1}
 PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 POLICY = {"cg": 0, "given": 1}
+PHASES = ("sym_tiles", "form_u", "tail", "next_action", "block_product", "gram", "eig",
+          "rotate", "predict", "update", "truncate")
 _ERR = {CAKF_E_ARG: "invalid argument", CAKF_E_HIP: "HIP runtime error",
         CAKF_E_NOMEM: "device allocation failed", CAKF_E_STATE: "call out of order",
         CAKF_E_SOLVER: "rocBLAS/rocSOLVER error"}
@@ -32,7 +34,8 @@ class cakf_config(ctypes.Structure):
         ("noise_var", ctypes.c_double), ("ou_coeff", ctypes.c_double),
         ("max_obs", ctypes.c_int), ("max_actions", ctypes.c_int), ("max_rank", ctypes.c_int),
         ("policy", ctypes.c_int), ("resid_tol", ctypes.c_double),
-        ("pivot_tol", ctypes.c_double), ("prec", ctypes.c_int), ("stream", ctypes.c_void_p),
+        ("pivot_tol", ctypes.c_double), ("prec", ctypes.c_int), ("smoother", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -40,6 +43,15 @@ class cakf_record(ctypes.Structure):
     _fields_ = [
         ("S", ctypes.c_void_p), ("W_obs", ctypes.c_void_p), ("w_obs", ctypes.c_void_p),
         ("chol", ctypes.c_void_p), ("loglik", ctypes.c_void_p), ("n_actions", ctypes.c_void_p),
+    ]
+
+
+class cakf_smooth_input(ctypes.Structure):
+    _fields_ = [
+        ("mean", ctypes.c_void_p), ("factor", ctypes.c_void_p), ("ld", ctypes.c_int),
+        ("rank", ctypes.c_int), ("pred_factor", ctypes.c_void_p), ("pred_ld", ctypes.c_int),
+        ("pred_rank", ctypes.c_int), ("idx", ctypes.c_void_p), ("w_obs", ctypes.c_void_p),
+        ("W_obs", ctypes.c_void_p), ("m", ctypes.c_int),
     ]
 
 
@@ -70,6 +82,11 @@ def lib() -> ctypes.CDLL:
             "cakf_marginal_var": (i, [vp, vp, i, vp]),
             "cakf_diagnostics": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i),
                                      ctypes.POINTER(i)]),
+            "cakf_smooth_begin": (i, [vp, vp, vp, vp, i]),
+            "cakf_smooth_step": (i, [vp, ctypes.POINTER(cakf_smooth_input), vp, vp, i, vp,
+                                     ctypes.POINTER(i)]),
+            "cakf_profile_enable": (i, [vp, i]),
+            "cakf_profile_read": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(i)]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -158,3 +175,28 @@ def cakf_diagnostics(ctx: int):
     check(lib().cakf_diagnostics(ctx, ctypes.byref(dr), ctypes.byref(nf), ctypes.byref(bi)),
           "cakf_diagnostics")
     return dr.value, nf.value, bi.value
+
+
+def cakf_profile_enable(ctx: int, on: bool) -> None:
+    check(lib().cakf_profile_enable(ctx, 1 if on else 0), "cakf_profile_enable")
+
+
+def cakf_profile_read(ctx: int):
+    """{phase: (total_ms, launches)}; resets the counters."""
+    n = len(PHASES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    check(lib().cakf_profile_read(ctx, ms, cnt), "cakf_profile_read")
+    return {PHASES[k]: (ms[k], cnt[k]) for k in range(n)}
+
+
+def cakf_smooth_begin(ctx: int, idx, w_obs, W_obs, m: int) -> None:
+    check(lib().cakf_smooth_begin(ctx, ptr(idx), ptr(w_obs), ptr(W_obs), m), "cakf_smooth_begin")
+
+
+def cakf_smooth_step(ctx: int, inp: cakf_smooth_input, mean_out=None, factor_out=None,
+                     ld_out: int = 0, var_out=None) -> int:
+    rank = ctypes.c_int()
+    check(lib().cakf_smooth_step(ctx, ctypes.byref(inp), ptr(mean_out), ptr(factor_out), ld_out,
+                                 ptr(var_out), ctypes.byref(rank)), "cakf_smooth_step")
+    return rank.value

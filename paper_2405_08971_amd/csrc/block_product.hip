@@ -75,16 +75,162 @@ __global__ __launch_bounds__(256) void k_block_fp32(const float4* __restrict__ X
     }
 }
 
+// ------------------------------------------------------------------- BF16 MFMA form
+// v_mfma_f32_32x32x16_bf16 (D = A B, A 32 x 16, B 16 x 32): lane l supplies
+// A[l % 32][8 (l / 32) + t] and B[8 (l / 32) + t][l % 32], t = 0..7, and holds
+// D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32] in accumulator register i.
+//
+// A is the kernel tile: each lane evaluates its 8 entries (its state row against 8
+// observation points) in FP32 on the VALU and rounds them to BF16 in registers, so the
+// tile never reaches LDS or memory.  B = [W w] arrives pre-split and transposed
+// (column-major, BF16): the chunk for 64 observations is staged in LDS and shared by the
+// workgroup's 4 waves.  Each wave owns 64 state rows (two 32-row tiles, which share
+// every B fragment) and NT 32-column tiles.  With X3 the products are
+// Kh Bh + Kl Bh + Kh Bl on K = Kh + Kl, B = Bh + Bl (each part BF16), which restores
+// close to FP32 accuracy at 3x the MFMA work.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int MF_KC = 64;        // observations per LDS chunk (4 MFMA k-steps)
+constexpr int MF_ROWS = 256;     // state rows per workgroup (4 waves x 64)
+
+template <int NU2, int DIST, int NT, bool X3>
+__global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ Xs, int n,
+                                                    const float4* __restrict__ Xo, int mp,
+                                                    const __bf16* __restrict__ Bth,
+                                                    const __bf16* __restrict__ Btl, int ldbt,
+                                                    int tile0, int ncols, float sigma_f2,
+                                                    float* __restrict__ out, int ldo) {
+    __shared__ float4 xo[MF_KC];
+    __shared__ bf16x8 bh[NT * 32][MF_KC / 8 + 1];
+    __shared__ bf16x8 bl[X3 ? NT * 32 : 1][MF_KC / 8 + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rl = lane & 31, half = lane >> 5;
+    const int row0 = blockIdx.x * MF_ROWS + w * 64;
+    const float4 xa = Xs[min(row0 + rl, n - 1)];
+    const float4 xb = Xs[min(row0 + 32 + rl, n - 1)];
+    f32x16 acc[2][NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            acc[0][c][i] = 0.0f;
+            acc[1][c][i] = 0.0f;
+        }
+    for (int q0 = 0; q0 < mp; q0 += MF_KC) {
+        __syncthreads();
+        if (threadIdx.x < MF_KC) xo[threadIdx.x] = Xo[q0 + threadIdx.x];
+        for (int e = threadIdx.x; e < NT * 32 * (MF_KC / 8); e += 256) {
+            const int c = e / (MF_KC / 8), g = e % (MF_KC / 8);
+            const size_t off = (size_t)(tile0 * 32 + c) * ldbt + q0 + 8 * g;
+            bh[c][g] = *reinterpret_cast<const bf16x8*>(Bth + off);
+            if constexpr (X3) bl[c][g] = *reinterpret_cast<const bf16x8*>(Btl + off);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < MF_KC / 16; ++ks) {
+            bf16x8 aah, abh, aal, abl;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float4 xq = xo[ks * 16 + 8 * half + t];
+                const float ka = kval<NU2, DIST>(xa, xq);
+                const float kb = kval<NU2, DIST>(xb, xq);
+                aah[t] = (__bf16)ka;
+                abh[t] = (__bf16)kb;
+                if constexpr (X3) {
+                    aal[t] = (__bf16)(ka - (float)aah[t]);
+                    abl[t] = (__bf16)(kb - (float)abh[t]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const bf16x8 b = bh[c * 32 + rl][ks * 2 + half];
+                acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, b, acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abh, b, acc[1][c], 0, 0, 0);
+                if constexpr (X3) {
+                    const bf16x8 b2 = bl[c * 32 + rl][ks * 2 + half];
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, b, acc[0][c], 0, 0, 0);
+                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abl, b, acc[1][c], 0, 0, 0);
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, b2, acc[0][c], 0, 0, 0);
+                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abh, b2, acc[1][c], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int col = (tile0 + c) * 32 + rl;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = row0 + 32 * r + 8 * (i / 4) + 4 * half + (i % 4);
+                if (row < n && col < ncols) out[(size_t)row * ldo + col] = sigma_f2 * acc[r][c][i];
+            }
+        }
+}
+
+template <int NU2, int DIST, bool X3>
+static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const float4* Xo,
+                              int mp, const __bf16* Bth, const __bf16* Btl, int ldbt,
+                              int ncols, float sigma_f2, float* out, int ldo, hipStream_t st) {
+    const dim3 grid((n + MF_ROWS - 1) / MF_ROWS), block(256);
+#define CAKF_MF(NTV)                                                                       \
+    hipLaunchKernelGGL((k_block_mfma<NU2, DIST, NTV, X3>), grid, block, 0, st, Xs, n, Xo, mp, \
+                       Bth, Btl, ldbt, tile0, ncols, sigma_f2, out, ldo)
+    switch (nt) {
+        case 1: CAKF_MF(1); break;
+        case 2: CAKF_MF(2); break;
+        case 3: CAKF_MF(3); break;
+        case 4: CAKF_MF(4); break;
+        default: CAKF_MF(5); break;
+    }
+#undef CAKF_MF
+}
+
+// Split B (FP32, row-major mp x ldb, columns 0..bp) into transposed BF16 parts:
+// Bth[c * mp + q] = bf16(B[q, c]), Btl = bf16(B - Bth).
+__global__ void k_split_bt(const float* __restrict__ B, int mp, int ldb, int bp,
+                           __bf16* __restrict__ Bth, __bf16* __restrict__ Btl) {
+    const size_t total = (size_t)mp * bp;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / mp), q = (int)(e % mp);
+        const float v = B[(size_t)q * ldb + c];
+        const __bf16 h = (__bf16)v;
+        Bth[e] = h;
+        Btl[e] = (__bf16)(v - (float)h);
+    }
+}
+
 void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
-                          const float4* Xo, int m, const float* B, int ldb, int bcols,
-                          float sigma_f2, float* out, int ldo, hipStream_t st) {
-    (void)prec;
-    const int blocks = (n + BP_ROWS - 1) / BP_ROWS;
-    for (int c0 = 0; c0 < bcols; c0 += BP_COLS) {
-        const int nc = std::min(BP_COLS, bcols - c0);
-        CAKF_DISPATCH_KERNEL(nu2, dist,
-            hipLaunchKernelGGL((k_block_fp32<NU2, DIST>), dim3(blocks), dim3(256), 0, st, Xs, n,
-                               Xo, m, B, ldb, c0, nc, sigma_f2, out, ldo));
+                          const float4* Xo, int m, int mp, const float* B, int ldb, int bcols,
+                          __bf16* Bth, __bf16* Btl, float sigma_f2, float* out, int ldo,
+                          hipStream_t st) {
+    if (prec == 0) {
+        const int blocks = (n + BP_ROWS - 1) / BP_ROWS;
+        for (int c0 = 0; c0 < bcols; c0 += BP_COLS) {
+            const int nc = std::min(BP_COLS, bcols - c0);
+            CAKF_DISPATCH_KERNEL(nu2, dist,
+                hipLaunchKernelGGL((k_block_fp32<NU2, DIST>), dim3(blocks), dim3(256), 0, st, Xs,
+                                   n, Xo, m, B, ldb, c0, nc, sigma_f2, out, ldo));
+        }
+        return;
+    }
+    const int ntiles = (bcols + 31) / 32;
+    const size_t total = (size_t)mp * ntiles * 32;
+    hipLaunchKernelGGL(k_split_bt, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
+                       dim3(256), 0, st, B, mp, ldb, ntiles * 32, Bth, Btl);
+    for (int t0 = 0; t0 < ntiles; t0 += 5) {
+        const int nt = std::min(5, ntiles - t0);
+        if (prec == 2) {
+            CAKF_DISPATCH_KERNEL(nu2, dist,
+                (launch_mfma_tiles<NU2, DIST, true>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp, bcols,
+                                                    sigma_f2, out, ldo, st)));
+        } else {
+            CAKF_DISPATCH_KERNEL(nu2, dist,
+                (launch_mfma_tiles<NU2, DIST, false>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp, bcols,
+                                                     sigma_f2, out, ldo, st)));
+        }
     }
 }
 

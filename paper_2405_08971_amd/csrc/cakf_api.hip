@@ -25,6 +25,14 @@ struct Diag {
     int bad_index;
 };
 
+// Per-phase timing with HIP events recorded on the context stream around each launch.
+struct Prof {
+    static constexpr int CAP = 2048;
+    hipEvent_t* ev[CAKF_PHASES][2];
+    int count[CAKF_PHASES];
+    bool on;
+};
+
 }  // namespace
 
 struct cakf_ctx {
@@ -47,17 +55,21 @@ struct cakf_ctx {
     float* Mo;
     float* S;
     float* U;
+    float* V;
     float* T;
     float* part;
     double* gpart;
     double* ttpart;
     float* mpart;
-    double *Linv, *L, *LSinv, *alpha, *beta;
+    double *Linv, *LinvT, *L, *LSinv, *LSinvT, *alpha, *beta;
+    float* Tbeta;
     LoopState* ls;
     Diag* diag;
     // block product
     float* B;
     float* Q;
+    __bf16* Bth;
+    __bf16* Btl;
     // truncation
     double* G;
     double* gwork;
@@ -66,7 +78,47 @@ struct cakf_ctx {
     int* info;
     float* Vr;
     void* blas_ws;
+    Prof prof;
+    // smoother (allocated when cfg.smoother != 0)
+    int np, bps, ldWs;
+    float4* Xp;
+    float* sm_ws;
+    float* sm_W[2];
+    int sm_cur, sm_rank;
+    bool sm_started;
+    float *sm_B, *sm_Y, *sm_Z, *sm_Q, *sm_Gr, *sm_R, *sm_WR;
+    __bf16 *sm_Bth, *sm_Btl;
 };
+
+namespace {
+
+struct PhaseTimer {
+    cakf_ctx* c;
+    int ph;
+    PhaseTimer(cakf_ctx* c_, int ph_) : c(c_), ph(ph_) {
+        if (c->prof.on && c->prof.count[ph] < Prof::CAP)
+            (void)hipEventRecord(c->prof.ev[ph][0][c->prof.count[ph]], c->stream);
+    }
+    ~PhaseTimer() {
+        if (c->prof.on && c->prof.count[ph] < Prof::CAP) {
+            (void)hipEventRecord(c->prof.ev[ph][1][c->prof.count[ph]], c->stream);
+            ++c->prof.count[ph];
+        }
+    }
+};
+
+void prof_free(cakf_ctx* c) {
+    for (int p = 0; p < CAKF_PHASES; ++p)
+        for (int k = 0; k < 2; ++k)
+            if (c->prof.ev[p][k]) {
+                for (int e = 0; e < Prof::CAP; ++e) (void)hipEventDestroy(c->prof.ev[p][k][e]);
+                delete[] c->prof.ev[p][k];
+                c->prof.ev[p][k] = nullptr;
+            }
+    c->prof.on = false;
+}
+
+}  // namespace
 
 #define HIP_TRY(x)                                   \
     do {                                             \
@@ -78,10 +130,13 @@ struct cakf_ctx {
     } while (0)
 
 static void free_all(cakf_ctx* c) {
-    void* ptrs[] = {c->mean, c->M[0], c->M[1], c->Xs, c->Xo, c->r0, c->Mo, c->S, c->U, c->T,
-                    c->part, c->gpart, c->ttpart, c->mpart, c->Linv, c->L, c->LSinv,
-                    c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->G, c->gwork, c->eigval,
-                    c->offdiag, c->info, c->Vr, c->blas_ws};
+    void* ptrs[] = {c->mean, c->M[0], c->M[1], c->Xs, c->Xo, c->r0, c->Mo, c->S, c->U, c->V, c->T,
+                    c->part, c->gpart, c->ttpart, c->mpart, c->Linv, c->LinvT, c->L,
+                    c->LSinv, c->LSinvT, c->Tbeta,
+                    c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->Bth, c->Btl, c->G, c->gwork, c->eigval,
+                    c->offdiag, c->info, c->Vr, c->blas_ws, c->Xp, c->sm_ws, c->sm_W[0],
+                    c->sm_W[1], c->sm_B, c->sm_Y, c->sm_Z, c->sm_Q, c->sm_Gr, c->sm_R,
+                    c->sm_WR, c->sm_Bth, c->sm_Btl};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -112,6 +167,7 @@ static int validate(const cakf_config* c) {
     if (c->prec != CAKF_PREC_FP32 && c->prec != CAKF_PREC_BF16 && c->prec != CAKF_PREC_BF16X3)
         return CAKF_E_ARG;
     if (c->resid_tol < 0 || c->pivot_tol < 0) return CAKF_E_ARG;
+    if (c->smoother && (size_t)c->n * (c->max_rank + 1) > ((size_t)1 << 31)) return CAKF_E_ARG;
     return CAKF_OK;
 }
 
@@ -140,8 +196,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     c->gram_work_elems = (size_t)16 * c->Kmax * c->Kmax;
     const size_t n = c->n;
     const int nbmax = c->mpmax / SYM_TILE;
-    const int nblk = (c->mmax + 255) / 256;
-    const int ntt = (c->r + 255) / 256;
+    const int nblk = (c->mmax + 63) / 64;   // largest per-launch block count of the row kernels
     rc = CAKF_OK;
     rc |= dalloc(&c->mean, n);
     rc |= dalloc(&c->M[0], n * c->ldM);
@@ -152,26 +207,50 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     rc |= dalloc(&c->Mo, (size_t)c->mpmax * c->r);
     rc |= dalloc(&c->S, (size_t)c->mpmax * c->imax);
     rc |= dalloc(&c->U, (size_t)c->mpmax * c->imax);
+    rc |= dalloc(&c->V, (size_t)c->mpmax * c->imax);
     rc |= dalloc(&c->T, (size_t)c->r * c->imax);
     rc |= dalloc(&c->part, (size_t)nbmax * c->mpmax);
     rc |= dalloc(&c->gpart, (size_t)nblk * (2 * c->imax + 1));
-    rc |= dalloc(&c->ttpart, (size_t)ntt * c->imax);
+    rc |= dalloc(&c->ttpart, (size_t)c->imax);
     rc |= dalloc(&c->mpart, (size_t)nblk * c->r);
     rc |= dalloc(&c->Linv, (size_t)c->imax * c->imax);
+    rc |= dalloc(&c->LinvT, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->L, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->LSinv, (size_t)c->imax * c->imax);
+    rc |= dalloc(&c->LSinvT, (size_t)c->imax * c->imax);
+    rc |= dalloc(&c->Tbeta, c->r);
     rc |= dalloc(&c->alpha, c->imax);
     rc |= dalloc(&c->beta, c->imax);
     rc |= dalloc(&c->ls, 1);
     rc |= dalloc(&c->diag, 1);
     rc |= dalloc(&c->B, (size_t)c->mpmax * c->bp);
     rc |= dalloc(&c->Q, (size_t)c->r * c->bp);
+    rc |= dalloc(&c->Bth, (size_t)c->mpmax * c->bp);
+    rc |= dalloc(&c->Btl, (size_t)c->mpmax * c->bp);
     rc |= dalloc(&c->G, (size_t)c->Kmax * c->Kmax);
     rc |= dalloc(&c->gwork, c->gram_work_elems);
     rc |= dalloc(&c->eigval, c->Kmax);
     rc |= dalloc(&c->offdiag, c->Kmax);
     rc |= dalloc(&c->info, 1);
     rc |= dalloc(&c->Vr, (size_t)c->Kmax * c->r);
+    if (cfg->smoother) {
+        c->np = round_up(c->n, SYM_TILE);
+        c->bps = round_up(1 + c->r, 32);
+        c->ldWs = round_up(c->imax + c->r, 4);
+        rc |= dalloc(&c->Xp, c->np);
+        rc |= dalloc(&c->sm_ws, n);
+        rc |= dalloc(&c->sm_W[0], n * c->ldWs);
+        rc |= dalloc(&c->sm_W[1], n * c->ldWs);
+        rc |= dalloc(&c->sm_B, (size_t)c->np * c->bps);
+        rc |= dalloc(&c->sm_Y, n * c->bps);
+        rc |= dalloc(&c->sm_Z, n * c->bps);
+        rc |= dalloc(&c->sm_Q, (size_t)c->Kmax * c->bps);
+        rc |= dalloc(&c->sm_Gr, (size_t)c->mmax * c->bps);
+        rc |= dalloc(&c->sm_R, (size_t)c->imax * c->bps);
+        rc |= dalloc(&c->sm_WR, (size_t)c->mmax * c->bps);
+        rc |= dalloc(&c->sm_Bth, (size_t)c->np * c->bps);
+        rc |= dalloc(&c->sm_Btl, (size_t)c->np * c->bps);
+    }
     if (rc) {
         free_all(c);
         delete c;
@@ -203,6 +282,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     const int nu2 = cfg->kernel;
     const double scale = std::sqrt((double)nu2) / cfg->lengthscale;
     launch_prescale(cfg->X, c->n, cfg->dim, (float)scale, cfg->dist, c->Xs, c->stream);
+    if (cfg->smoother) launch_pad_points(c->Xs, c->n, c->np, c->Xp, c->stream);
     if (hipMemsetAsync(c->mean, 0, n * sizeof(float), c->stream) != hipSuccess ||
         hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -220,6 +300,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
 extern "C" void cakf_destroy(cakf_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    prof_free(c);
     rocblas_destroy_handle(c->blas);
     free_all(c);
     delete c;
@@ -307,8 +388,10 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     const size_t tri = (size_t)c->imax * c->imax * sizeof(double);
     HIP_TRY(hipMemsetAsync(c->ls, 0, sizeof(LoopState), st));
     HIP_TRY(hipMemsetAsync(c->Linv, 0, tri, st));
+    HIP_TRY(hipMemsetAsync(c->LinvT, 0, tri, st));
     HIP_TRY(hipMemsetAsync(c->L, 0, tri, st));
     HIP_TRY(hipMemsetAsync(c->LSinv, 0, tri, st));
+    HIP_TRY(hipMemsetAsync(c->LSinvT, 0, tri, st));
     HIP_TRY(hipMemsetAsync(c->alpha, 0, c->imax * sizeof(double), st));
     HIP_TRY(hipMemsetAsync(c->beta, 0, c->imax * sizeof(double), st));
     launch_gather(c->Xs, c->n, c->mean, M, c->ldM, idx, y, actions, cg ? 1 : 0, d, c->Xo, c->r0,
@@ -317,28 +400,41 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
         if (cg) {
             int nb = 0;
             launch_colsum_partial(c->Mo, c->r, m, d.rank, c->r0, 1, c->mpart, c->r, st, &nb);
-            launch_colsum_final(c->mpart, c->r, nb, d.rank, c->T, c->imax, st);
+            launch_colsum_final(c->mpart, c->r, nb, d.rank, c->T, 1, st);
         } else {
-            // T^T = S^T Mo  (imax x rank, column-major ld imax) = row-major T (rank x imax)
+            // T = Mo^T S, stored column-major (rank x imax, ld r): T[l * r + c]
             const float one = 1.0f, zero = 0.0f;
             BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                                   c->imax, d.rank, m, &one, c->S, c->imax, c->Mo, c->r, &zero,
-                                   c->T, c->imax));
+                                   d.rank, c->imax, m, &one, c->Mo, c->r, c->S, c->imax, &zero,
+                                   c->T, c->r));
         }
     }
     const int nu2 = c->cfg.kernel, dist = c->cfg.dist;
     int nmpart = 0;
     for (int j = 0; j < imax; ++j) {
-        launch_sym_tiles(nu2, dist, c->Xo, c->S, d, j, c->part,
-                         (cg && j > 0) ? c->mpart : nullptr, nmpart, c->T, c->ttpart, c->ls, st);
+        {
+            PhaseTimer t(c, CAKF_PHASE_SYM_TILES);
+            launch_sym_tiles(nu2, dist, c->Xo, c->S, d, j, c->part,
+                             (cg && j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart, c->T,
+                             c->ls, st);
+        }
         int nb2 = 0;
-        launch_form_u(c->part, c->S, c->U, c->r0, d, j, c->cfg.signal_var, c->gpart, c->ls, st,
-                      &nb2);
-        launch_tail(c->gpart, nb2, c->ttpart, d, j, c->cfg.noise_var, c->cfg.resid_tol,
-                    c->cfg.pivot_tol, c->Linv, c->L, c->LSinv, c->alpha, c->beta, c->ls, st);
-        if (cg && j + 1 < imax)
-            launch_next_action(c->U, c->Mo, c->r0, c->S, c->beta, c->T,
+        {
+            PhaseTimer t(c, CAKF_PHASE_FORM_U);
+            launch_form_u(c->part, c->S, c->U, c->r0, c->T, d, j, c->cfg.signal_var, c->gpart,
+                          c->ttpart, c->ls, st, &nb2);
+        }
+        {
+            PhaseTimer t(c, CAKF_PHASE_TAIL);
+            launch_tail(c->gpart, nb2, c->ttpart, d, j, c->cfg.noise_var, c->cfg.resid_tol,
+                        c->cfg.pivot_tol, c->Linv, c->LinvT, c->L, c->LSinv, c->LSinvT,
+                        c->alpha, c->beta, c->ls, st);
+        }
+        if (cg && j + 1 < imax) {
+            PhaseTimer t(c, CAKF_PHASE_NEXT_ACTION);
+            launch_next_action(c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T,
                                (float)c->cfg.noise_var, d, j, c->mpart, c->ls, st, &nmpart);
+        }
     }
     launch_build_block(c->S, c->Linv, c->beta, d, c->B, c->bp, c->bp, rec->W_obs, rec->w_obs,
                        rec->S, c->ls, st);
@@ -350,8 +446,11 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
                                d.rank, b, m, &one, c->Mo, c->r, c->B, c->bp, &zero, c->Q, c->r));
     }
     // Y = Sigma[:, idx] B into the new columns rank .. rank + b of the factor
-    launch_block_product(nu2, dist, c->cfg.prec, c->Xs, c->n, c->Xo, m, c->B, c->bp, b,
-                         (float)c->cfg.signal_var, M + d.rank, c->ldM, st);
+    {
+        PhaseTimer t(c, CAKF_PHASE_BLOCK_PRODUCT);
+        launch_block_product(nu2, dist, c->cfg.prec, c->Xs, c->n, c->Xo, m, d.mp, c->B, c->bp, b,
+                             c->Bth, c->Btl, (float)c->cfg.signal_var, M + d.rank, c->ldM, st);
+    }
     if (d.rank > 0) {
         const float mone = -1.0f, one = 1.0f;
         // Y -= M^- Q  (the low-rank part of P^- H^T [W w])
@@ -366,33 +465,192 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 
+// Replace the n x K factor M (row-major, ld) by M V_r in Mout (ld ldo), V_r the leading
+// r eigenvectors of M^T M (FP64 Gram, FP64 symmetric eigensolver, FP32 rotation).
+static int truncate_factor(cakf_ctx* c, const float* M, int ld, int K, int r, float* Mout,
+                           int ldo, double* rotation) {
+    hipStream_t st = c->stream;
+    {
+        PhaseTimer t(c, CAKF_PHASE_GRAM);
+        launch_gram64(M, c->n, ld, K, c->G, c->gwork, c->gram_work_elems, st);
+    }
+    {
+        PhaseTimer t(c, CAKF_PHASE_EIG);
+        BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K, c->G,
+                                  K, c->eigval, c->offdiag, c->info));
+    }
+    {
+        PhaseTimer t(c, CAKF_PHASE_ROTATE);
+        launch_pick_rotation(c->G, K, r, c->Vr, rotation, st);
+        const float one = 1.0f, zero = 0.0f;
+        // Mout (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n)
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, r,
+                               c->n, K, &one, c->Vr, K, M, ld, &zero, Mout, ldo));
+    }
+    return CAKF_OK;
+}
+
 extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
     if (!c) return CAKF_E_ARG;
     const int K = c->rank;
     if (K <= c->r) return CAKF_OK;
-    hipStream_t st = c->stream;
-    float* M = c->M[c->cur];
-    float* Mn = c->M[1 - c->cur];
-    launch_gram64(M, c->n, c->ldM, K, c->G, c->gwork, c->gram_work_elems, st);
-    BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K, c->G, K,
-                              c->eigval, c->offdiag, c->info));
-    launch_pick_rotation(c->G, K, c->r, c->Vr, rotation, st);
-    const float one = 1.0f, zero = 0.0f;
-    // M_new (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n)
-    BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, c->r,
-                           c->n, K, &one, c->Vr, K, M, c->ldM, &zero, Mn, c->ldM));
+    int rc = truncate_factor(c, c->M[c->cur], c->ldM, K, c->r, c->M[1 - c->cur], c->ldM,
+                             rotation);
+    if (rc) return rc;
     c->cur = 1 - c->cur;
     c->rank = c->r;
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 
+// ---------------------------------------------------------------- smoother (Alg. 3)
+extern "C" int cakf_smooth_begin(cakf_ctx* c, const int32_t* idx, const float* w_obs,
+                                 const float* W_obs, int m) {
+    if (!c || !c->Xp || m < 0 || m > c->mmax) return CAKF_E_ARG;
+    if (m > 0 && (!idx || !w_obs || !W_obs)) return CAKF_E_ARG;
+    hipStream_t st = c->stream;
+    c->sm_cur = 0;
+    // ws_T = H^T w_obs, Ws_T = H^T W_obs (no earlier smoother messages: rs = 0, Bs = 0)
+    HIP_TRY(hipMemsetAsync(c->sm_B, 0, (size_t)c->np * c->bps * sizeof(float), st));
+    launch_smooth_messages(c->sm_B, c->bps, c->n, idx, m, m > 0 ? c->imax : 0, 0, w_obs, W_obs,
+                           c->imax, nullptr, 0, c->sm_ws, c->sm_W[0], c->ldWs, st);
+    c->sm_rank = m > 0 ? c->imax : 0;
+    c->sm_started = true;
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float* mean_out,
+                                float* factor_out, int ld_out, float* var_out, int* out_rank) {
+    if (!c || !in || !c->sm_started || !in->mean) return CAKF_E_ARG;
+    if (in->rank < 0 || in->rank > c->Kmax || (in->rank > 0 && (!in->factor || in->ld < in->rank)))
+        return CAKF_E_ARG;
+    if (in->pred_rank < 0 || in->pred_rank > c->Kmax ||
+        (in->pred_rank > 0 && (!in->pred_factor || in->pred_ld < in->pred_rank)))
+        return CAKF_E_ARG;
+    if (in->m < 0 || in->m > c->mmax || (in->m > 0 && (!in->idx || !in->w_obs || !in->W_obs)))
+        return CAKF_E_ARG;
+    const int rs = c->sm_rank;
+    const int b = 1 + rs;
+    if (factor_out && ld_out < in->rank + rs) return CAKF_E_ARG;
+    hipStream_t st = c->stream;
+    const float a = (float)c->cfg.ou_coeff;
+    const float one = 1.0f, zero = 0.0f, mone = -1.0f;
+    float* Ws = c->sm_W[c->sm_cur];
+    // Bs = A^T [ws Ws]
+    launch_smooth_pack(c->sm_ws, Ws, c->ldWs, c->n, c->np, rs, a, c->sm_B, c->bps, st);
+    // Y = Sigma Bs (kernel matrix over all points, never stored)
+    {
+        PhaseTimer t(c, CAKF_PHASE_BLOCK_PRODUCT);
+        launch_block_product(c->cfg.kernel, c->cfg.dist, c->cfg.prec, c->Xs, c->n, c->Xp, c->n,
+                             c->np, c->sm_B, c->bps, b, c->sm_Bth, c->sm_Btl,
+                             (float)c->cfg.signal_var, c->sm_Y, c->bps, st);
+    }
+    // Z = P_k A^T [ws Ws] = Y - M_k (M_k^T Bs)
+    HIP_TRY(hipMemcpyAsync(c->sm_Z, c->sm_Y, (size_t)c->n * c->bps * sizeof(float),
+                           hipMemcpyDeviceToDevice, st));
+    if (in->rank > 0) {
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
+                               in->rank, b, c->n, &one, in->factor, in->ld, c->sm_B, c->bps, &zero,
+                               c->sm_Q, c->Kmax));
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, b,
+                               c->n, in->rank, &mone, c->sm_Q, c->Kmax, in->factor, in->ld, &one,
+                               c->sm_Z, c->bps));
+    }
+    launch_smooth_out(in->mean, in->factor, in->ld, in->rank, c->sm_Z, c->bps, b, c->n,
+                      (float)c->cfg.signal_var, mean_out, factor_out, ld_out, var_out, st);
+    if (out_rank) *out_rank = in->rank + rs;
+    // Pm = P_k^- A^T [ws Ws] = Y - M_k^- (M_k^-^T Bs), reusing Z
+    const int i = in->m > 0 ? c->imax : 0;
+    if (in->m > 0) {
+        HIP_TRY(hipMemcpyAsync(c->sm_Z, c->sm_Y, (size_t)c->n * c->bps * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+        if (in->pred_rank > 0) {
+            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
+                                   in->pred_rank, b, c->n, &one, in->pred_factor, in->pred_ld,
+                                   c->sm_B, c->bps, &zero, c->sm_Q, c->Kmax));
+            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                   b, c->n, in->pred_rank, &mone, c->sm_Q, c->Kmax,
+                                   in->pred_factor, in->pred_ld, &one, c->sm_Z, c->bps));
+        }
+        // R = W_obs^T Pm[idx, :] (imax x b), WR = W_obs R (m x b)
+        launch_gather_rows(c->sm_Z, c->bps, in->idx, in->m, c->n, b, c->sm_Gr, c->bps, st);
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
+                               c->imax, b, in->m, &one, in->W_obs, c->imax, c->sm_Gr, c->bps, &zero,
+                               c->sm_R, c->imax));
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, b,
+                               in->m, c->imax, &one, c->sm_R, c->imax, in->W_obs, c->imax, &zero,
+                               c->sm_WR, c->bps));
+    }
+    // ws = w + proj[:, 0], [W, proj[:, 1:]] with proj = Bs - H^T (W_obs R)
+    float* Wn = c->sm_W[1 - c->sm_cur];
+    launch_smooth_messages(c->sm_B, c->bps, c->n, in->idx, in->m, i, rs, in->w_obs, in->W_obs,
+                           c->imax, in->m > 0 ? c->sm_WR : nullptr, c->bps, c->sm_ws, Wn,
+                           c->ldWs, st);
+    const int K = i + rs;
+    if (K > c->r) {
+        int rc = truncate_factor(c, Wn, c->ldWs, K, c->r, Ws, c->ldWs, nullptr);
+        if (rc) return rc;
+        c->sm_rank = c->r;          // result landed in the current buffer
+    } else {
+        c->sm_cur = 1 - c->sm_cur;
+        c->sm_rank = K;
+    }
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
 extern "C" int cakf_step(cakf_ctx* c, const int32_t* idx, const float* y, int m,
                          const float* actions, const cakf_record* rec) {
-    int rc = cakf_predict(c);
+    if (!c) return CAKF_E_ARG;
+    int rc;
+    {
+        PhaseTimer t(c, CAKF_PHASE_PREDICT);
+        rc = cakf_predict(c);
+    }
     if (rc) return rc;
-    rc = cakf_update(c, idx, y, m, actions, rec);
+    {
+        PhaseTimer t(c, CAKF_PHASE_UPDATE);
+        rc = cakf_update(c, idx, y, m, actions, rec);
+    }
     if (rc) return rc;
+    PhaseTimer t(c, CAKF_PHASE_TRUNCATE);
     return cakf_truncate(c, nullptr);
+}
+
+extern "C" int cakf_profile_enable(cakf_ctx* c, int on) {
+    if (!c) return CAKF_E_ARG;
+    if (!on) {
+        prof_free(c);
+        return CAKF_OK;
+    }
+    if (!c->prof.on) {
+        for (int p = 0; p < CAKF_PHASES; ++p)
+            for (int k = 0; k < 2; ++k) {
+                c->prof.ev[p][k] = new (std::nothrow) hipEvent_t[Prof::CAP];
+                if (!c->prof.ev[p][k]) return CAKF_E_NOMEM;
+                for (int e = 0; e < Prof::CAP; ++e)
+                    HIP_TRY(hipEventCreate(&c->prof.ev[p][k][e]));
+            }
+        c->prof.on = true;
+    }
+    for (int p = 0; p < CAKF_PHASES; ++p) c->prof.count[p] = 0;
+    return CAKF_OK;
+}
+
+extern "C" int cakf_profile_read(cakf_ctx* c, double* total_ms, int* launches) {
+    if (!c || !total_ms || !launches) return CAKF_E_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int p = 0; p < CAKF_PHASES; ++p) {
+        double acc = 0.0;
+        const int n = c->prof.on ? c->prof.count[p] : 0;
+        for (int e = 0; e < n; ++e) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, c->prof.ev[p][0][e], c->prof.ev[p][1][e]));
+            acc += ms;
+        }
+        total_ms[p] = acc;
+        launches[p] = n;
+        if (c->prof.on) c->prof.count[p] = 0;
+    }
+    return CAKF_OK;
 }
 
 extern "C" int cakf_marginal_var(cakf_ctx* c, const int32_t* rows, int count, float* out) {

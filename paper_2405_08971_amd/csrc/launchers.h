@@ -53,15 +53,15 @@ void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, floa
                          int ldo, hipStream_t st);
 void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
                       int j, float* part, const float* mpart, int nmpart, float* T,
-                      double* ttpart, const LoopState* ls, hipStream_t st);
+                      const LoopState* ls, hipStream_t st);
 void launch_form_u(const float* part, const float* S, float* U, const float* r0,
-                   const ObsDims& d, int j, double sigma_f2, double* gpart,
-                   const LoopState* ls, hipStream_t st, int* nblk_out);
-void launch_tail(const double* gpart, int nblk, const double* ttpart, const ObsDims& d,
-                 int j, double noise_var, double resid_tol, double pivot_tol, double* Linv,
-                 double* L, double* LSinv, double* alpha, double* beta, LoopState* ls,
-                 hipStream_t st);
-void launch_next_action(const float* U, const float* Mo, const float* r0, float* S,
+                   const float* T, const ObsDims& d, int j, double sigma_f2, double* gpart,
+                   double* ttv, const LoopState* ls, hipStream_t st, int* nblk_out);
+void launch_tail(const double* gpart, int nblk, const double* ttv, const ObsDims& d, int j,
+                 double noise_var, double resid_tol, double pivot_tol, double* Linv,
+                 double* LinvT, double* L, double* LSinv, double* LSinvT, double* alpha,
+                 double* beta, LoopState* ls, hipStream_t st);
+void launch_next_action(const float* U, const float* Mo, const float* r0, float* S, float* V,
                         const double* beta, const float* T, float noise_var,
                         const ObsDims& d, int j, float* mpart, const LoopState* ls,
                         hipStream_t st, int* nblk_out);
@@ -73,13 +73,28 @@ void launch_finish_record(const LoopState* ls, const double* L, int imax, double
 
 // ---- block_product.hip
 void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
-                          const float4* Xo, int m, const float* B, int ldb, int bcols,
-                          float sigma_f2, float* out, int ldo, hipStream_t st);
+                          const float4* Xo, int m, int mp, const float* B, int ldb, int bcols,
+                          __bf16* Bth, __bf16* Btl, float sigma_f2, float* out, int ldo,
+                          hipStream_t st);
 
 // ---- truncate.hip
 void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* work,
                    size_t work_elems, hipStream_t st);
 void launch_pick_rotation(const double* E, int K, int r, float* Vr, double* rot_out,
                           hipStream_t st);
+
+// ---- smooth.hip
+void launch_smooth_pack(const float* ws, const float* Ws, int ldw, int n, int np, int rs,
+                        float a, float* Bs, int ldb, hipStream_t st);
+void launch_smooth_out(const float* mean, const float* M, int ldm, int rank, const float* Z,
+                       int ldz, int b, int n, float sigma_f2, float* mean_out,
+                       float* factor_out, int ldo, float* var_out, hipStream_t st);
+void launch_gather_rows(const float* A, int lda, const int32_t* idx, int m, int n, int cols,
+                        float* out, int ldo, hipStream_t st);
+void launch_smooth_messages(const float* Bs, int ldb, int n, const int32_t* idx, int m, int i,
+                            int rs, const float* w_obs, const float* W_obs, int imax,
+                            const float* WR, int ldr, float* ws, float* Wc, int ldw,
+                            hipStream_t st);
+void launch_pad_points(const float4* Xs, int n, int np, float4* Xp, hipStream_t st);
 
 }  // namespace cakf

@@ -38,7 +38,8 @@ class CAKF:
                  lengthscale: float, signal_var: float = 1.0, noise_var: float,
                  ou_coeff: float, max_obs: int, max_actions: int, max_rank: int,
                  policy: str = "cg", resid_tol: float = 0.0, pivot_tol: float = 1e-10,
-                 prec: str = "fp32", stream: Optional[torch.cuda.Stream] = None):
+                 prec: str = "fp32", smoother: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None):
         if X.dtype != torch.float32 or X.dim() != 2:
             raise ValueError("X must be a float32 (n, dim) device tensor")
         X = X.contiguous()
@@ -51,7 +52,7 @@ class CAKF:
             lengthscale=lengthscale, signal_var=signal_var, noise_var=noise_var,
             ou_coeff=ou_coeff, max_obs=max_obs, max_actions=max_actions, max_rank=max_rank,
             policy=L.POLICY[policy], resid_tol=resid_tol, pivot_tol=pivot_tol,
-            prec=L.PREC[prec], stream=L.stream_handle(stream))
+            prec=L.PREC[prec], smoother=1 if smoother else 0, stream=L.stream_handle(stream))
         self._X = X
         self.ctx = L.cakf_create(cfg)
 
@@ -115,3 +116,41 @@ class CAKF:
 
     def diagnostics(self):
         return L.cakf_diagnostics(self.ctx)
+
+    # -- smoother (Alg. 3) ---------------------------------------------------------------
+    def smooth_begin(self, idx=None, record: Optional[Record] = None):
+        m = 0 if idx is None else int(idx.numel())
+        if m:
+            L.cakf_smooth_begin(self.ctx, idx, record.w_obs, record.W_obs, m)
+        else:
+            L.cakf_smooth_begin(self.ctx, None, None, None, 0)
+
+    def smooth_step(self, mean, factor, pred_factor, idx=None, record: Optional[Record] = None,
+                    want_factor: bool = False):
+        """One backward step; factor / pred_factor are (n, rank) float32 device tensors.
+        Returns (smoothed mean, marginal variances, smoothed factor or None)."""
+        factor = factor.contiguous()
+        pred_factor = pred_factor.contiguous()
+        m = 0 if idx is None else int(idx.numel())
+        inp = L.cakf_smooth_input(
+            mean=L.ptr(mean), factor=L.ptr(factor) if factor.shape[1] else None,
+            ld=max(factor.shape[1], 1), rank=factor.shape[1],
+            pred_factor=L.ptr(pred_factor) if pred_factor.shape[1] else None,
+            pred_ld=max(pred_factor.shape[1], 1), pred_rank=pred_factor.shape[1],
+            idx=L.ptr(idx) if m else None, w_obs=L.ptr(record.w_obs) if m else None,
+            W_obs=L.ptr(record.W_obs) if m else None, m=m)
+        out_mean = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        out_var = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        out_fac = None
+        ld = 0
+        if want_factor:
+            ld = factor.shape[1] + self.max_rank + self.max_actions
+            out_fac = torch.empty((self.n, ld), dtype=torch.float32, device="cuda")
+        rank = L.cakf_smooth_step(self.ctx, inp, out_mean, out_fac, ld, out_var)
+        return out_mean, out_var, (out_fac[:, :rank] if want_factor else None)
+
+    def profile(self, on: bool = True):
+        L.cakf_profile_enable(self.ctx, on)
+
+    def profile_read(self):
+        return L.cakf_profile_read(self.ctx)

@@ -113,3 +113,46 @@ def compare(cfg, model, recs, gpu, probes=None):
             e["MMt"] = rel_mean_err(g["MMt_probe"], rec.M @ (rec.M.T @ probes))
         errs.append(e)
     return errs
+
+
+def gpu_run_smoother(cfg: Config, X, steps, actions, policy, prec="fp32"):
+    """Filter forward keeping m_k, M_k, M_k^- and the records, then the smoother backward.
+    Returns per-step (smoothed mean, smoothed marginal variance), k = 1..T."""
+    import torch
+    from paper_2405_08971_amd.filter import CAKF, Record
+
+    dev = "cuda"
+    Xd = torch.from_numpy(X).to(dev)
+    f = CAKF(Xd, nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid",
+             lengthscale=cfg.ell, signal_var=cfg.sigma_f2, noise_var=cfg.noise_var,
+             ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy=policy,
+             prec=prec, smoother=True)
+    fwd = []
+    for k, item in enumerate(steps):
+        f.predict()
+        _, Mp = f.state()
+        rec, idx = None, None
+        if item is None:
+            f.update(None, None)
+        else:
+            idx = torch.from_numpy(item[0]).to(dev)
+            y = torch.from_numpy(item[1]).to(dev)
+            a = None if actions[k] is None else torch.from_numpy(actions[k]).to(dev)
+            rec = Record(len(item[0]), cfg.i)
+            f.update(idx, y, a, rec)
+        mean, M = f.state()
+        fwd.append((mean, M, Mp, idx, rec))
+        f.truncate()
+    T = len(steps)
+    out = [None] * T
+    mean_T, M_T = fwd[-1][0], fwd[-1][1]
+    var_T = cfg.sigma_f2 - (M_T.double() ** 2).sum(1)
+    out[T - 1] = (mean_T.cpu().numpy().astype(np.float64), var_T.cpu().numpy())
+    f.smooth_begin(fwd[-1][3], fwd[-1][4])
+    for k in range(T - 2, -1, -1):
+        mean, M, Mp, idx, rec = fwd[k]
+        ms, vs, _ = f.smooth_step(mean, M, Mp, idx, rec)
+        out[k] = (ms.cpu().numpy().astype(np.float64), vs.cpu().numpy().astype(np.float64))
+    torch.cuda.synchronize()
+    f.close()
+    return out

@@ -109,3 +109,21 @@ def test_deterministic_bitwise():
         assert np.array_equal(ga["mean"], gb["mean"])
         assert np.array_equal(ga["var_trunc"], gb["var_trunc"])
         assert ga["loglik"] == gb["loglik"]
+
+
+# Bars for the BF16 block product.  The split form (Kh Bh + Kl Bh + Kh Bl) is the mode
+# that meets the 1e-3 requirement of the BF16 path, and is held to 1e-4 here (measured
+# about 1e-5).  Plain BF16 rounding of the kernel tile and of [W w] leaves 2e-3 to 7e-3
+# on these cases: it does NOT meet 1e-3 and is held only to 1e-2.
+PREC_TOL = {"bf16": 1e-2, "bf16x3": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("case", ["sphere_m32", "plane_m52"])
+def test_given_actions_bf16_block_product_matches_oracle(case, prec):
+    cfg = small_config(case, **CASES[case])
+    X, steps, actions = inputs(cfg, seed=8, missing_steps=(3,) if cfg.T >= 5 else ())
+    model, recs = oracle_run(cfg, X, steps, actions, "given")
+    probes = np.random.default_rng(1).standard_normal((cfg.n, 3))
+    gpu = gpu_run(cfg, X, steps, actions, "given", prec, probes=probes)
+    _check(compare(cfg, model, recs, gpu, probes), PREC_TOL[prec])
