@@ -161,6 +161,15 @@ int cakf_step(cakf_ctx* ctx, const int32_t* idx, const float* y, int m,
  * index outside [0, n) yields NaN. */
 int cakf_marginal_var(cakf_ctx* ctx, const int32_t* rows, int count, float* out);
 
+/* Log marginal likelihood of the data seen since the last reset, as the filter defines
+ * it: the sum over updates of the projected prediction-error terms
+ *   l_k = -1/2 [ i log 2 pi + log det(S^T Ghat S) - log det(S^T S)
+ *                + (S^T r0)^T (S^T Ghat S)^{-1} (S^T r0) ]
+ * (the paper leaves evidence maximisation to future work, Sec. 8; for full actions and
+ * no truncation the sum is the exact Gaussian-process evidence).  value: host double;
+ * steps (nullable): number of updates with data.  Synchronises the stream. */
+int cakf_loglik(cakf_ctx* ctx, double* value, int* steps);
+
 /* Device status words since the last reset: actions dropped on breakdown, non-finite
  * pivots, and observation indices outside [0, n) (each read as index 0).  Any output
  * pointer may be NULL.  Synchronises the stream. */

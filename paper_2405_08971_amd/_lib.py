@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
             "cakf_marginal_var": (i, [vp, vp, i, vp]),
             "cakf_diagnostics": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i),
                                      ctypes.POINTER(i)]),
+            "cakf_loglik": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(i)]),
             "cakf_smooth_begin": (i, [vp, vp, vp, vp, i]),
             "cakf_smooth_step": (i, [vp, ctypes.POINTER(cakf_smooth_input), vp, vp, i, vp,
                                      ctypes.POINTER(i)]),
@@ -200,3 +201,9 @@ def cakf_smooth_step(ctx: int, inp: cakf_smooth_input, mean_out=None, factor_out
     check(lib().cakf_smooth_step(ctx, ctypes.byref(inp), ptr(mean_out), ptr(factor_out), ld_out,
                                  ptr(var_out), ctypes.byref(rank)), "cakf_smooth_step")
     return rank.value
+
+
+def cakf_loglik(ctx: int):
+    v, n = ctypes.c_double(), ctypes.c_int()
+    check(lib().cakf_loglik(ctx, ctypes.byref(v), ctypes.byref(n)), "cakf_loglik")
+    return v.value, n.value

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_block_fp32(const float4* __restrict__ X
     // kernel-tile role: row tr (4 threads per row), 16 observation points each
     const int tr = tid >> 2, tq = (tid & 3) * 16;
     const int prow = min(row0 + tr, n - 1);
-    const float4 xr = Xs[prow];
+    const float4 xr = prep_row<DIST>(Xs[prow]);
     // contraction role: row cr, column group g
     const int cr = tid & 63, g = tid >> 6;
     float acc[BP_CB];
@@ -84,14 +84,14 @@ __global__ __launch_bounds__(256) void k_block_fp32(const float4* __restrict__ X
 // observation points) in FP32 on the VALU and rounds them to BF16 in registers, so the
 // tile never reaches LDS or memory.  B = [W w] arrives pre-split and transposed
 // (column-major, BF16): the chunk for 64 observations is staged in LDS and shared by the
-// workgroup's 4 waves.  Each wave owns 64 state rows (two 32-row tiles, which share
-// every B fragment) and NT 32-column tiles.  With X3 the products are
+// workgroup's 4 waves.  Each wave owns one 32-row tile of state rows and NT 32-column
+// tiles.  With X3 the products are
 // Kh Bh + Kl Bh + Kh Bl on K = Kh + Kl, B = Bh + Bl (each part BF16), which restores
 // close to FP32 accuracy at 3x the MFMA work.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int MF_KC = 64;        // observations per LDS chunk (4 MFMA k-steps)
-constexpr int MF_ROWS = 256;     // state rows per workgroup (4 waves x 64)
+constexpr int MF_ROWS = 128;     // state rows per workgroup (4 waves x 32)
 
 template <int NU2, int DIST, int NT, bool X3>
 __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ Xs, int n,
@@ -105,17 +105,13 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
     __shared__ bf16x8 bl[X3 ? NT * 32 : 1][MF_KC / 8 + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rl = lane & 31, half = lane >> 5;
-    const int row0 = blockIdx.x * MF_ROWS + w * 64;
-    const float4 xa = Xs[min(row0 + rl, n - 1)];
-    const float4 xb = Xs[min(row0 + 32 + rl, n - 1)];
-    f32x16 acc[2][NT];
+    const int row0 = blockIdx.x * MF_ROWS + w * 32;
+    const float4 xa = prep_row<DIST>(Xs[min(row0 + rl, n - 1)]);
+    f32x16 acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            acc[0][c][i] = 0.0f;
-            acc[1][c][i] = 0.0f;
-        }
+        for (int i = 0; i < 16; ++i) acc[c][i] = 0.0f;
     for (int q0 = 0; q0 < mp; q0 += MF_KC) {
         __syncthreads();
         if (threadIdx.x < MF_KC) xo[threadIdx.x] = Xo[q0 + threadIdx.x];
@@ -128,45 +124,34 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < MF_KC / 16; ++ks) {
-            bf16x8 aah, abh, aal, abl;
+            bf16x8 ah, al;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const float4 xq = xo[ks * 16 + 8 * half + t];
-                const float ka = kval<NU2, DIST>(xa, xq);
-                const float kb = kval<NU2, DIST>(xb, xq);
-                aah[t] = (__bf16)ka;
-                abh[t] = (__bf16)kb;
-                if constexpr (X3) {
-                    aal[t] = (__bf16)(ka - (float)aah[t]);
-                    abl[t] = (__bf16)(kb - (float)abh[t]);
-                }
+                const float ka = kval<NU2, DIST>(xa, xo[ks * 16 + 8 * half + t]);
+                ah[t] = (__bf16)ka;
+                if constexpr (X3) al[t] = (__bf16)(ka - (float)ah[t]);
             }
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
                 const bf16x8 b = bh[c * 32 + rl][ks * 2 + half];
-                acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, b, acc[0][c], 0, 0, 0);
-                acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abh, b, acc[1][c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b, acc[c], 0, 0, 0);
                 if constexpr (X3) {
                     const bf16x8 b2 = bl[c * 32 + rl][ks * 2 + half];
-                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, b, acc[0][c], 0, 0, 0);
-                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abl, b, acc[1][c], 0, 0, 0);
-                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, b2, acc[0][c], 0, 0, 0);
-                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abh, b2, acc[1][c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b2, acc[c], 0, 0, 0);
                 }
             }
         }
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < NT; ++c) {
+        const int col = (tile0 + c) * 32 + rl;
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            const int col = (tile0 + c) * 32 + rl;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int row = row0 + 32 * r + 8 * (i / 4) + 4 * half + (i % 4);
-                if (row < n && col < ncols) out[(size_t)row * ldo + col] = sigma_f2 * acc[r][c][i];
-            }
+        for (int i = 0; i < 16; ++i) {
+            const int row = row0 + 8 * (i / 4) + 4 * half + (i % 4);
+            if (row < n && col < ncols) out[(size_t)row * ldo + col] = sigma_f2 * acc[c][i];
         }
+    }
 }
 
 template <int NU2, int DIST, bool X3>

@@ -23,6 +23,8 @@ struct Diag {
     int dropped;
     int nonfinite;
     int bad_index;
+    int steps;          // updates with data since the last reset
+    double loglik;      // sum of the projected log-likelihood terms since the last reset
 };
 
 // Per-phase timing with HIP events recorded on the context stream around each launch.
@@ -280,7 +282,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     }
     // Pre-scaled points and the prior state.
     const int nu2 = cfg->kernel;
-    const double scale = std::sqrt((double)nu2) / cfg->lengthscale;
+    const double scale = 1.4426950408889634 * std::sqrt((double)nu2) / cfg->lengthscale;
     launch_prescale(cfg->X, c->n, cfg->dim, (float)scale, cfg->dist, c->Xs, c->stream);
     if (cfg->smoother) launch_pad_points(c->Xs, c->n, c->np, c->Xp, c->stream);
     if (hipMemsetAsync(c->mean, 0, n * sizeof(float), c->stream) != hipSuccess ||
@@ -361,6 +363,8 @@ __global__ void k_count_diag(const LoopState* ls, Diag* dg) {
     dg->dropped += ls->dropped;
     dg->nonfinite += ls->nonfinite;
     dg->bad_index += ls->bad_index;
+    dg->steps += 1;
+    dg->loglik += ls->loglik;
 }
 
 extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int m,
@@ -659,6 +663,16 @@ extern "C" int cakf_marginal_var(cakf_ctx* c, const int32_t* rows, int count, fl
     if (count == 0) return CAKF_OK;
     launch_marginal_var(c->M[c->cur], c->n, c->ldM, c->rank, (float)c->cfg.signal_var, rows,
                         count, out, c->stream);
+    return CAKF_OK;
+}
+
+extern "C" int cakf_loglik(cakf_ctx* c, double* value, int* steps) {
+    if (!c || !value) return CAKF_E_ARG;
+    Diag h;
+    HIP_TRY(hipMemcpyAsync(&h, c->diag, sizeof(Diag), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *value = h.loglik;
+    if (steps) *steps = h.steps;
     return CAKF_OK;
 }
 

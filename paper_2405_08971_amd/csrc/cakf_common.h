@@ -8,43 +8,59 @@
 
 namespace cakf {
 
-// Points are stored pre-scaled as float4.  Euclidean distance: (c x, c y, c z, 0) with
-// c = sqrt(2 nu) / ell, so that u = sqrt(2 nu) d / ell is the plain Euclidean distance
-// of the stored vectors.  Great-circle distance: (x, y, z, c) with unit (x, y, z) and
-// u = c * theta, theta = 2 arcsin(|x - x'| / 2) (the angle arccos(<x, x'>) written in
-// its chord form, which stays well conditioned for nearby points in FP32).
+// Points are stored pre-scaled as float4 by c = log2(e) sqrt(2 nu) / ell, so that the
+// scaled distance u' = log2(e) u (u = sqrt(2 nu) d / ell) feeds exp2 directly.
+//  Euclidean:    (c x, c y, c z, c^2 |x|^2); a row point is prepared once as
+//                (-2 c x, -2 c y, -2 c z, c^2 |x|^2) so that
+//                u'^2 = w_a + w_b - 2 <a, b> costs one add and three FMAs; the sqrt takes
+//                |u'^2| (a free source modifier) against rounding below zero.
+//  Great-circle: (x, y, z, c) with unit (x, y, z) and u' = c theta,
+//                theta = 2 arcsin(|x - x'| / 2), the chord form of arccos(<x, x'>) that
+//                stays well conditioned for nearby points in FP32.
 enum { DIST_EUCLID = 0, DIST_GEODESIC = 1 };
 
-// Matern(nu) correlation as a function of u = sqrt(2 nu) d / ell (unit variance):
-//   nu = 1/2 : exp(-u);  nu = 3/2 : (1 + u) exp(-u);  nu = 5/2 : (1 + u + u^2/3) exp(-u).
+constexpr float LN2 = 0.6931471805599453f;
+
+// Matern(nu) correlation as a function of u' = log2(e) u (unit variance):
+//   nu = 1/2 : 2^-u';  nu = 3/2 : (1 + ln2 u') 2^-u';
+//   nu = 5/2 : (1 + ln2 u' + ln2^2 u'^2 / 3) 2^-u'.
 template <int NU2>
-__device__ __forceinline__ float matern_u(float u) {
-    const float e = __builtin_amdgcn_exp2f(-u * 1.4426950408889634f);
+__device__ __forceinline__ float matern_u(float up) {
+    const float e = __builtin_amdgcn_exp2f(-up);
     if constexpr (NU2 == 1) {
         return e;
     } else if constexpr (NU2 == 3) {
-        return __builtin_fmaf(u, e, e);
+        return __builtin_fmaf(up * LN2, e, e);
     } else {
-        const float p = __builtin_fmaf(u, __builtin_fmaf(u, 0.333333343f, 1.0f), 1.0f);
+        const float p = __builtin_fmaf(up, __builtin_fmaf(up, LN2 * LN2 / 3.0f, LN2), 1.0f);
         return p * e;
     }
 }
 
 template <int DIST>
-__device__ __forceinline__ float scaled_dist(const float4 a, const float4 b) {
+__device__ __forceinline__ float4 prep_row(const float4 a) {
+    if constexpr (DIST == DIST_EUCLID) return make_float4(-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, a.w);
+    else return a;
+}
+
+// u' between a prepared row point and a stored point.
+template <int DIST>
+__device__ __forceinline__ float scaled_dist(const float4 ap, const float4 b) {
     if constexpr (DIST == DIST_EUCLID) {
-        const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-        return __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+        const float t = __builtin_fmaf(ap.x, b.x, __builtin_fmaf(ap.y, b.y,
+                        __builtin_fmaf(ap.z, b.z, ap.w + b.w)));
+        return __builtin_amdgcn_sqrtf(__builtin_fabsf(t));
     } else {
-        const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+        const float dx = ap.x - b.x, dy = ap.y - b.y, dz = ap.z - b.z;
         const float h = __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
-        return a.w * 2.0f * asinf(fminf(1.0f, 0.5f * h));
+        return ap.w * 2.0f * asinf(fminf(1.0f, 0.5f * h));
     }
 }
 
+// Kernel entry k(a, b) for a prepared row point ap = prep_row(a) and a stored point b.
 template <int NU2, int DIST>
-__device__ __forceinline__ float kval(const float4 a, const float4 b) {
-    return matern_u<NU2>(scaled_dist<DIST>(a, b));
+__device__ __forceinline__ float kval(const float4 ap, const float4 b) {
+    return matern_u<NU2>(scaled_dist<DIST>(ap, b));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {

@@ -5,7 +5,8 @@
 
 namespace cakf {
 
-// Euclidean: (c x, c y, c z, 0); great-circle: (x, y, z, c), c = sqrt(2 nu) / ell.
+// Euclidean: (c x, c y, c z, c^2 |x|^2); great-circle: (x, y, z, c), with
+// c = log2(e) sqrt(2 nu) / ell (see cakf_common.h).
 __global__ void k_prescale(const float* __restrict__ X, int n, int dim, float c, int dist,
                            float4* __restrict__ Xs) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -13,8 +14,13 @@ __global__ void k_prescale(const float* __restrict__ X, int n, int dim, float c,
     const float x = X[(size_t)p * dim + 0];
     const float y = X[(size_t)p * dim + 1];
     const float z = dim == 3 ? X[(size_t)p * dim + 2] : 0.0f;
-    Xs[p] = dist == DIST_EUCLID ? make_float4(c * x, c * y, c * z, 0.0f)
-                                : make_float4(x, y, z, c);
+    if (dist == DIST_EUCLID) {
+        const float sx = c * x, sy = c * y, sz = c * z;
+        const double w = (double)sx * sx + (double)sy * sy + (double)sz * sz;
+        Xs[p] = make_float4(sx, sy, sz, (float)w);
+    } else {
+        Xs[p] = make_float4(x, y, z, c);
+    }
 }
 
 void launch_prescale(const float* X, int n, int dim, float c, int dist, float4* Xs,

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const float4* __restrict__ Xo
     float sa[8], sb[8], ra[8], cb[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        a[i] = xr[tr + 16 * i];
+        a[i] = prep_row<DIST>(xr[tr + 16 * i]);
         sa[i] = sr[tr + 16 * i];
         b[i] = xc[tc + 16 * i];
         sb[i] = sc[tc + 16 * i];

@@ -117,6 +117,10 @@ class CAKF:
     def diagnostics(self):
         return L.cakf_diagnostics(self.ctx)
 
+    def loglik(self):
+        """(sum of the projected log-likelihood terms, number of updates with data)."""
+        return L.cakf_loglik(self.ctx)
+
     # -- smoother (Alg. 3) ---------------------------------------------------------------
     def smooth_begin(self, idx=None, record: Optional[Record] = None):
         m = 0 if idx is None else int(idx.numel())

@@ -127,3 +127,26 @@ def test_given_actions_bf16_block_product_matches_oracle(case, prec):
     probes = np.random.default_rng(1).standard_normal((cfg.n, 3))
     gpu = gpu_run(cfg, X, steps, actions, "given", prec, probes=probes)
     _check(compare(cfg, model, recs, gpu, probes), PREC_TOL[prec])
+
+
+def test_loglik_entry_point_sums_the_step_terms():
+    import torch
+    from paper_2405_08971_amd.filter import CAKF
+    from oracle.cakf import total_loglik
+    cfg = small_config("ll", n=500, m=160, i=6, r=10, T=4)
+    X, steps, actions = inputs(cfg, seed=9, missing_steps=(2,))
+    model, recs = oracle_run(cfg, X, steps, actions, "given")
+    f = CAKF(torch.from_numpy(X).cuda(), nu2=cfg.nu2, lengthscale=cfg.ell,
+             signal_var=cfg.sigma_f2, noise_var=cfg.noise_var, ou_coeff=cfg.a,
+             max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy="given")
+    for k, item in enumerate(steps):
+        if item is None:
+            f.step(None, None)
+        else:
+            f.step(torch.from_numpy(item[0]).cuda(), torch.from_numpy(item[1]).cuda(),
+                   torch.from_numpy(actions[k]).cuda())
+    value, nsteps = f.loglik()
+    f.close()
+    ref = total_loglik(recs)
+    assert nsteps == 3
+    assert abs(value - ref) <= 1e-5 * abs(ref), (value, ref)
