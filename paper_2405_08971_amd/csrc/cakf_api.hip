@@ -43,7 +43,7 @@ struct cakf_ctx {
     rocblas_handle blas;
     int device;
     // dimensions
-    int n, r, imax, mmax, mpmax, ldM, bp, Kmax;
+    int n, r, imax, mmax, mpmax, ldM, bp, Kmax, ldmo, gs;
     size_t gram_work_elems;
     // state
     float* mean;
@@ -60,11 +60,12 @@ struct cakf_ctx {
     float* V;
     float* T;
     float* part;
-    double* gpart;
+    double* cpart;     // next_action's per-block column products
+    double* colvec;    // the reduced column products of the current action
+    double* fupart;    // form_u's per-block partial sums of s_j^T u_j
     double* ttpart;
     float* mpart;
     double *Linv, *LinvT, *L, *LSinv, *LSinvT, *alpha, *beta;
-    float* Tbeta;
     LoopState* ls;
     Diag* diag;
     // block product
@@ -133,8 +134,8 @@ void prof_free(cakf_ctx* c) {
 
 static void free_all(cakf_ctx* c) {
     void* ptrs[] = {c->mean, c->M[0], c->M[1], c->Xs, c->Xo, c->r0, c->Mo, c->S, c->U, c->V, c->T,
-                    c->part, c->gpart, c->ttpart, c->mpart, c->Linv, c->LinvT, c->L,
-                    c->LSinv, c->LSinvT, c->Tbeta,
+                    c->part, c->cpart, c->colvec, c->fupart, c->ttpart, c->mpart, c->Linv,
+                    c->LinvT, c->L, c->LSinv, c->LSinvT,
                     c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->Bth, c->Btl, c->G, c->gwork, c->eigval,
                     c->offdiag, c->info, c->Vr, c->blas_ws, c->Xp, c->sm_ws, c->sm_W[0],
                     c->sm_W[1], c->sm_B, c->sm_Y, c->sm_Z, c->sm_Q, c->sm_Gr, c->sm_R,
@@ -195,10 +196,13 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     c->ldM = round_up(c->r + c->imax + 1, 4);
     c->bp = round_up(c->imax + 1, 32);
     c->Kmax = c->r + c->imax;
+    c->ldmo = round_up(c->r, 8);
+    c->gs = 2 * c->imax + 2;
     c->gram_work_elems = (size_t)16 * c->Kmax * c->Kmax;
     const size_t n = c->n;
     const int nbmax = c->mpmax / SYM_TILE;
-    const int nblk = (c->mmax + 63) / 64;   // largest per-launch block count of the row kernels
+    // largest block count of a next_action launch (the column-product and Mo^T s partials)
+    const int nablk = std::max(next_action_blocks(c->mmax, 4, 4), next_action_blocks(c->mmax, 16, 1));
     rc = CAKF_OK;
     rc |= dalloc(&c->mean, n);
     rc |= dalloc(&c->M[0], n * c->ldM);
@@ -206,21 +210,22 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     rc |= dalloc(&c->Xs, n);
     rc |= dalloc(&c->Xo, c->mpmax);
     rc |= dalloc(&c->r0, c->mpmax);
-    rc |= dalloc(&c->Mo, (size_t)c->mpmax * c->r);
+    rc |= dalloc(&c->Mo, (size_t)c->mpmax * c->ldmo);
     rc |= dalloc(&c->S, (size_t)c->mpmax * c->imax);
     rc |= dalloc(&c->U, (size_t)c->mpmax * c->imax);
     rc |= dalloc(&c->V, (size_t)c->mpmax * c->imax);
-    rc |= dalloc(&c->T, (size_t)c->r * c->imax);
+    rc |= dalloc(&c->T, (size_t)c->ldmo * c->imax);
     rc |= dalloc(&c->part, (size_t)nbmax * c->mpmax);
-    rc |= dalloc(&c->gpart, (size_t)nblk * (2 * c->imax + 1));
+    rc |= dalloc(&c->cpart, (size_t)nablk * c->gs);
+    rc |= dalloc(&c->colvec, (size_t)c->gs);
+    rc |= dalloc(&c->fupart, (size_t)(c->mpmax / 64));
     rc |= dalloc(&c->ttpart, (size_t)c->imax);
-    rc |= dalloc(&c->mpart, (size_t)nblk * c->r);
+    rc |= dalloc(&c->mpart, (size_t)std::max(nablk, (c->mmax + 255) / 256) * c->ldmo);
     rc |= dalloc(&c->Linv, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->LinvT, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->L, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->LSinv, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->LSinvT, (size_t)c->imax * c->imax);
-    rc |= dalloc(&c->Tbeta, c->r);
     rc |= dalloc(&c->alpha, c->imax);
     rc |= dalloc(&c->beta, c->imax);
     rc |= dalloc(&c->ls, 1);
@@ -387,7 +392,7 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     d.mp = round_up(m, SYM_TILE);
     d.imax = c->imax;
     d.rank = c->rank;
-    d.ldmo = c->r;
+    d.ldmo = c->ldmo;
     float* M = c->M[c->cur];
     const size_t tri = (size_t)c->imax * c->imax * sizeof(double);
     HIP_TRY(hipMemsetAsync(c->ls, 0, sizeof(LoopState), st));
@@ -403,41 +408,46 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     if (d.rank > 0) {
         if (cg) {
             int nb = 0;
-            launch_colsum_partial(c->Mo, c->r, m, d.rank, c->r0, 1, c->mpart, c->r, st, &nb);
-            launch_colsum_final(c->mpart, c->r, nb, d.rank, c->T, 1, st);
+            launch_colsum_partial(c->Mo, c->ldmo, m, d.rank, c->r0, 1, c->mpart, c->ldmo, st, &nb);
+            launch_colsum_final(c->mpart, c->ldmo, nb, d.rank, c->T, 1, st);
         } else {
-            // T = Mo^T S, stored column-major (rank x imax, ld r): T[l * r + c]
+            // T = Mo^T S, stored column-major (rank x imax, ld ldmo): T[l * ldmo + c]
             const float one = 1.0f, zero = 0.0f;
             BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                                   d.rank, c->imax, m, &one, c->Mo, c->r, c->S, c->imax, &zero,
-                                   c->T, c->r));
+                                   d.rank, c->imax, m, &one, c->Mo, c->ldmo, c->S, c->imax,
+                                   &zero, c->T, c->ldmo));
         }
     }
     const int nu2 = c->cfg.kernel, dist = c->cfg.dist;
-    int nmpart = 0;
+    const float noise = (float)c->cfg.noise_var;
+    // column products of s_0
+    int ncp = 0, nmpart = 0;
+    launch_next_action(0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise, d, 0, c->mpart,
+                       c->cpart, c->gs, c->ls, st, &ncp);
     for (int j = 0; j < imax; ++j) {
         {
             PhaseTimer t(c, CAKF_PHASE_SYM_TILES);
             launch_sym_tiles(nu2, dist, c->Xo, c->S, d, j, c->part,
                              (cg && j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart, c->T,
-                             c->ls, st);
+                             c->cpart, ncp, c->gs, c->colvec, c->ls, st);
         }
-        int nb2 = 0;
+        int nfu = 0;
         {
             PhaseTimer t(c, CAKF_PHASE_FORM_U);
-            launch_form_u(c->part, c->S, c->U, c->r0, c->T, d, j, c->cfg.signal_var, c->gpart,
-                          c->ttpart, c->ls, st, &nb2);
+            launch_form_u(c->part, c->S, c->U, c->T, d, j, c->cfg.signal_var, c->fupart,
+                          c->ttpart, c->ls, st, &nfu);
         }
         {
             PhaseTimer t(c, CAKF_PHASE_TAIL);
-            launch_tail(c->gpart, nb2, c->ttpart, d, j, c->cfg.noise_var, c->cfg.resid_tol,
-                        c->cfg.pivot_tol, c->Linv, c->LinvT, c->L, c->LSinv, c->LSinvT,
-                        c->alpha, c->beta, c->ls, st);
+            launch_tail(c->colvec, c->fupart, nfu, c->ttpart, d, j, c->cfg.noise_var,
+                        c->cfg.resid_tol, c->cfg.pivot_tol, c->Linv, c->LinvT, c->L, c->LSinv,
+                        c->LSinvT, c->alpha, c->beta, c->ls, st);
         }
-        if (cg && j + 1 < imax) {
+        if (j + 1 < imax) {
             PhaseTimer t(c, CAKF_PHASE_NEXT_ACTION);
-            launch_next_action(c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T,
-                               (float)c->cfg.noise_var, d, j, c->mpart, c->ls, st, &nmpart);
+            launch_next_action(cg ? 1 : 0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise,
+                               d, j + 1, c->mpart, c->cpart, c->gs, c->ls, st, &ncp);
+            nmpart = ncp;
         }
     }
     launch_build_block(c->S, c->Linv, c->beta, d, c->B, c->bp, c->bp, rec->W_obs, rec->w_obs,
@@ -447,7 +457,8 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
         const float one = 1.0f, zero = 0.0f;
         // Q = Mo^T B  (rank x b, column-major ld r)
         BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                               d.rank, b, m, &one, c->Mo, c->r, c->B, c->bp, &zero, c->Q, c->r));
+                               d.rank, b, m, &one, c->Mo, c->ldmo, c->B, c->bp, &zero, c->Q,
+                               c->r));
     }
     // Y = Sigma[:, idx] B into the new columns rank .. rank + b of the factor
     {

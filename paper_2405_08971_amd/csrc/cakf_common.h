@@ -57,22 +57,71 @@ __device__ __forceinline__ float scaled_dist(const float4 ap, const float4 b) {
     }
 }
 
+// u' from coordinate differences (Euclidean).  The dot-product form above leaves an
+// absolute error of order eps |x|^2 in u'^2, i.e. order sqrt(eps) |x| in u' near u' = 0;
+// the Matern-3/2 and -5/2 correlations are flat to first order there, Matern-1/2 is not,
+// so it takes the differences: b - a = b + ap / 2 with one rounding per coordinate.
+__device__ __forceinline__ float scaled_dist_diff(const float4 ap, const float4 b) {
+    const float dx = __builtin_fmaf(0.5f, ap.x, b.x);
+    const float dy = __builtin_fmaf(0.5f, ap.y, b.y);
+    const float dz = __builtin_fmaf(0.5f, ap.z, b.z);
+    return __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+}
+
 // Kernel entry k(a, b) for a prepared row point ap = prep_row(a) and a stored point b.
 template <int NU2, int DIST>
 __device__ __forceinline__ float kval(const float4 ap, const float4 b) {
-    return matern_u<NU2>(scaled_dist<DIST>(ap, b));
+    if constexpr (NU2 == 1 && DIST == DIST_EUCLID) return matern_u<NU2>(scaled_dist_diff(ap, b));
+    else return matern_u<NU2>(scaled_dist<DIST>(ap, b));
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, CAKF_WAVE);
+// Wave-wide sums with the result in every lane.  Within each row of 16 lanes the sum is
+// formed with DPP lane permutes (quad swaps, half-row and row mirrors); the four row sums
+// are then read out with readlane and added in a fixed order, so the result is
+// deterministic and identical in all lanes.
+namespace dpp {
+constexpr int QUAD_1032 = 0xB1;     // quad_perm [1, 0, 3, 2]
+constexpr int QUAD_2301 = 0x4E;     // quad_perm [2, 3, 0, 1]
+constexpr int ROW_HALF_MIRROR = 0x141;
+constexpr int ROW_MIRROR = 0x140;
+template <int CTRL>
+__device__ __forceinline__ float perm(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double perm(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFLL), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename F>
+__device__ __forceinline__ F row_sum(F v) {
+    v += perm<QUAD_1032>(v);
+    v += perm<QUAD_2301>(v);
+    v += perm<ROW_HALF_MIRROR>(v);
+    v += perm<ROW_MIRROR>(v);
     return v;
+}
+__device__ __forceinline__ float lane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+}  // namespace dpp
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v = dpp::row_sum(v);
+    return (dpp::lane(v, 0) + dpp::lane(v, 16)) + (dpp::lane(v, 32) + dpp::lane(v, 48));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, CAKF_WAVE);
-    return v;
+    v = dpp::row_sum(v);
+    return (dpp::lane(v, 0) + dpp::lane(v, 16)) + (dpp::lane(v, 32) + dpp::lane(v, 48));
 }
 
 }  // namespace cakf

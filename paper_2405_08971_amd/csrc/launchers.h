@@ -7,7 +7,16 @@
 namespace cakf {
 
 constexpr int SYM_TILE = 128;       // side of the symmetric kernel tiles of the action loop
-constexpr int ROWS_PER_WAVE = 64;   // observation rows per wave in the row kernels
+
+// Shape of the next_action launch: factor columns per lane (ldmo <= 64 CPL), action columns
+// per lane (imax <= 64 LPL) and rows per wave (fewer when the rows' registers are large).
+constexpr int next_action_cpl(int ldmo) { return ldmo <= 256 ? 4 : ldmo <= 512 ? 8 : 16; }
+constexpr int next_action_lpl(int imax) { return imax <= 64 ? 1 : imax <= 128 ? 2 : 4; }
+constexpr int next_action_rows_per_wave(int cpl, int lpl) { return (cpl > 8 || lpl > 2) ? 4 : 8; }
+constexpr int next_action_blocks(int m, int cpl, int lpl) {
+    return (m + 4 * next_action_rows_per_wave(cpl, lpl) - 1) /
+           (4 * next_action_rows_per_wave(cpl, lpl));
+}
 
 // Device-resident scalars of one update's action loop.
 struct LoopState {
@@ -29,7 +38,7 @@ struct ObsDims {
     int mp;       // m rounded up to SYM_TILE
     int imax;     // action budget; leading dimension of S, U, T and the FP64 triangles
     int rank;     // columns of the predictive factor
-    int ldmo;     // leading dimension of Mo (= max_rank)
+    int ldmo;     // leading dimension of Mo and T (max_rank rounded up to 8)
 };
 
 // ---- misc.hip
@@ -53,18 +62,19 @@ void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, floa
                          int ldo, hipStream_t st);
 void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
                       int j, float* part, const float* mpart, int nmpart, float* T,
+                      const double* cpart, int ncpart, int gs, double* colvec,
                       const LoopState* ls, hipStream_t st);
-void launch_form_u(const float* part, const float* S, float* U, const float* r0,
-                   const float* T, const ObsDims& d, int j, double sigma_f2, double* gpart,
-                   double* ttv, const LoopState* ls, hipStream_t st, int* nblk_out);
-void launch_tail(const double* gpart, int nblk, const double* ttv, const ObsDims& d, int j,
-                 double noise_var, double resid_tol, double pivot_tol, double* Linv,
-                 double* LinvT, double* L, double* LSinv, double* LSinvT, double* alpha,
-                 double* beta, LoopState* ls, hipStream_t st);
-void launch_next_action(const float* U, const float* Mo, const float* r0, float* S, float* V,
-                        const double* beta, const float* T, float noise_var,
-                        const ObsDims& d, int j, float* mpart, const LoopState* ls,
-                        hipStream_t st, int* nblk_out);
+void launch_form_u(const float* part, const float* S, float* U, const float* T,
+                   const ObsDims& d, int j, double sigma_f2, double* fupart, double* ttv,
+                   const LoopState* ls, hipStream_t st, int* nblk_out);
+void launch_tail(const double* colvec, const double* fupart, int nfu, const double* ttv,
+                 const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
+                 double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
+                 double* alpha, double* beta, LoopState* ls, hipStream_t st);
+void launch_next_action(int resid, const float* U, const float* Mo, const float* r0, float* S,
+                        float* V, const double* beta, const float* T, float noise_var,
+                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
+                        const LoopState* ls, hipStream_t st, int* nblk_out);
 void launch_build_block(const float* S, const double* Linv, const double* beta,
                         const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
                         float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st);

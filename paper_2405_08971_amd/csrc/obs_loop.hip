@@ -5,16 +5,24 @@
 // Gram matrix C = S^T Ghat S, Ghat = H P^- H^T + Lambda = sigma_f2 K(Xo, Xo)
 // - Mo Mo^T + noise_var I, Mo = H M^-.  Actions are chosen one at a time (the iterative
 // update of App. B); with the CG policy the next action is the current residual
-// (Sec. 3.3).  The kernels keep, per action s_j,
-//     u_j = sigma_f2 K(Xo, Xo) s_j   (U, m x i),   t_j = Mo^T s_j   (T, r x i),
-// so that column j of C is  S^T u_j - T^T t_j + noise_var S^T s_j  and the residual
-// after j+1 actions is r0 - (U - Mo T + noise_var S) beta with beta = C^{-1} S^T r0.  C is factorised incrementally in FP64 (C = L L^T with L^{-1}
-// kept explicitly); the Ghat-orthonormal directions of the iterative update are
-// S L^{-T} (App. B), which is what the block product consumes.
+// (Sec. 3.3).  The kernels keep, per action s_l,
+//     u_l = sigma_f2 K(Xo, Xo) s_l   (U, m x i),   t_l = Mo^T s_l   (T, r x i),
+// so that entry (l, j) of C is  g_l - t_l^T t_j + noise_var s_l^T s_j  with
+// g_l = s_l^T u_j = u_l^T s_j (K is symmetric).  The residual after j+1 actions is
+// r0 - (U - Mo T + noise_var S) beta with beta = C^{-1} S^T r0.  C is factorised
+// incrementally in FP64 (C = L L^T with L^{-1} kept explicitly); the Ghat-orthonormal
+// directions of the iterative update are S L^{-T} (App. B), which is what the block
+// product consumes.
 //
-// One iteration j launches: sym_tiles (u_j), form_u (u_j and the Gram partial sums),
-// tail (one FP64 block), next_action (CG only: s_{j+1}, V[:, j] = Mo t_j and partial
-// sums of Mo^T s_{j+1}).
+// Column j of C needs u_j only in its diagonal entry: every other entry, u_l^T s_j and
+// s_l^T s_j for l < j, and s_j^T s_j, r0^T s_j, is formed from rows that are already
+// loaded when s_j is produced.  One iteration j launches:
+//   sym_tiles    u_j tile sums; its first blocks finish the column products of s_j
+//                (and, CG, t_j = Mo^T s_j) from the previous launch's block partials;
+//   form_u       u_j = sum of the tile sums, and the partial sums of s_j^T u_j;
+//   tail         one FP64 block: column j of C, the Cholesky step, alpha and beta;
+//   next_action  CG: s_{j+1} = the residual, V[:, j] = Mo t_j, partial sums of
+//                Mo^T s_{j+1}; both policies: the column products of s_{j+1}.
 #include "cakf_common.h"
 #include "launchers.h"
 
@@ -136,42 +144,76 @@ void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, floa
 }
 
 // ----------------------------------------------------------- symmetric kernel matvec
+// out[pos] = sum over rows b < nrows of in[b * ld + pos] for the CR_POS positions pos0 +
+// [0, CR_POS) below npos: CR_GRP row groups with 8 independent FP64 accumulators each,
+// combined in a fixed order.  The result is valid in the threads of group 0.
+constexpr int CR_POS = 32, CR_GRP = 8;
+
+template <typename Tin>
+__device__ __forceinline__ double column_reduce(const Tin* __restrict__ in, size_t ld,
+                                                int nrows, int npos, int pos0,
+                                                double (*red)[CR_POS + 1]) {
+    const int pl = threadIdx.x % CR_POS, grp = threadIdx.x / CR_POS;
+    const int pos = pos0 + pl;
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    if (pos < npos) {
+        int b = grp;
+        for (; b + 7 * CR_GRP < nrows; b += 8 * CR_GRP) {
+            Tin v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = in[(size_t)(b + u * CR_GRP) * ld + pos];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += (double)v[u];
+        }
+        for (; b < nrows; b += CR_GRP) a[0] += (double)in[(size_t)b * ld + pos];
+    }
+    red[grp][pl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    __syncthreads();
+    double s = 0.0;
+    if (grp == 0) {
+#pragma unroll
+        for (int g = 0; g < CR_GRP; ++g) s += red[g][pl];
+    }
+    return s;
+}
+
 // u_j = K(Xo, Xo) s_j over the upper triangle of SYM_TILE x SYM_TILE tiles.  Tile (P, Q),
 // P <= Q, adds its row sums K_PQ s_Q to slot Q of block P and (P < Q) its column sums
 // K_PQ^T s_P to slot P of block Q; every (slot, block) pair is written exactly once, so
 // the reduction in form_u is deterministic.  Each thread evaluates an 8 x 8 set of
-// entries.  With mpart (CG policy, j > 0) the first n_extra blocks instead finish
-// t_j = Mo^T s_j (column j of T, stored column-major: T[l * ldmo + c]) from
-// next_action's per-block partial sums, 64 factor columns per block.
+// entries.  The first n_t + n_c blocks instead finish, from next_action's per-block
+// partial sums: (n_t) t_j = Mo^T s_j into column j of T (column-major, T[l * ldmo + c]);
+// (n_c) the column products of s_j into colvec, laid out as
+// [u_l^T s_j (l < j) | s_l^T s_j (l <= j) | r0^T s_j].
 template <int NU2, int DIST>
 __global__ __launch_bounds__(256) void k_sym_tiles(const float4* __restrict__ Xo,
                                                    const float* __restrict__ S, ObsDims d,
                                                    int j, float* __restrict__ part,
                                                    const float* __restrict__ mpart,
-                                                   int nmpart, int n_extra,
+                                                   int nmpart, int n_t,
                                                    float* __restrict__ T,
+                                                   const double* __restrict__ cpart,
+                                                   int ncpart, int gs, int n_c,
+                                                   double* __restrict__ colvec,
                                                    const LoopState* __restrict__ ls) {
     if (ls->stop) return;
+    const int n_extra = n_t + n_c;
     if ((int)blockIdx.x < n_extra) {
-        __shared__ double tred[4][64];
-        const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
-        const int c = blockIdx.x * 64 + cl;
-        double a8[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a8[u] = 0.0;
-        if (c < d.rank) {
-            int b = grp;
-            for (; b + 28 < nmpart; b += 32) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) a8[u] += mpart[(size_t)(b + 4 * u) * d.ldmo + c];
-            }
-            for (; b < nmpart; b += 4) a8[0] += mpart[(size_t)b * d.ldmo + c];
+        __shared__ double cred[CR_GRP][CR_POS + 1];
+        if ((int)blockIdx.x < n_t) {
+            const int pos0 = blockIdx.x * CR_POS;
+            const double v = column_reduce(mpart, (size_t)d.ldmo, nmpart, d.rank, pos0, cred);
+            if ((int)threadIdx.x < CR_POS && pos0 + (int)threadIdx.x < d.rank)
+                T[(size_t)j * d.ldmo + pos0 + threadIdx.x] = (float)v;
+        } else {
+            const int pos0 = (blockIdx.x - n_t) * CR_POS;
+            const int npos = 2 * j + 2;
+            const double v = column_reduce(cpart, (size_t)gs, ncpart, npos, pos0, cred);
+            if ((int)threadIdx.x < CR_POS && pos0 + (int)threadIdx.x < npos)
+                colvec[pos0 + threadIdx.x] = v;
         }
-        tred[grp][cl] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-        __syncthreads();
-        if (grp == 0 && c < d.rank)
-            T[(size_t)j * d.ldmo + c] =
-                (float)((tred[0][cl] + tred[1][cl]) + (tred[2][cl] + tred[3][cl]));
         return;
     }
     const int t = blockIdx.x - n_extra;
@@ -238,34 +280,32 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const float4* __restrict__ Xo
 
 void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
                       int j, float* part, const float* mpart, int nmpart, float* T,
+                      const double* cpart, int ncpart, int gs, double* colvec,
                       const LoopState* ls, hipStream_t st) {
     const int nb = d.mp / SYM_TILE;
     const int tiles = nb * (nb + 1) / 2;
-    const int n_extra = (mpart && nmpart > 0) ? (d.rank + 63) / 64 : 0;
+    const int n_t = (mpart && nmpart > 0) ? (d.rank + CR_POS - 1) / CR_POS : 0;
+    const int n_c = (2 * j + 2 + CR_POS - 1) / CR_POS;
     CAKF_DISPATCH_KERNEL(nu2, dist,
-        hipLaunchKernelGGL((k_sym_tiles<NU2, DIST>), dim3(tiles + n_extra), dim3(256), 0, st,
-                           Xo, S, d, j, part, mpart, nmpart, n_extra, T, ls));
+        hipLaunchKernelGGL((k_sym_tiles<NU2, DIST>), dim3(tiles + n_t + n_c), dim3(256), 0, st,
+                           Xo, S, d, j, part, mpart, nmpart, n_t, T, cpart, ncpart, gs, n_c,
+                           colvec, ls));
 }
 
 // ------------------------------------------------------------------------- form_u
-// u_j[p] = sigma_f2 * (sum over the nb slots of the tile partial sums, FP64), i.e.
-// U = Sigma[idx, idx] S, stored in U[:, j]; per-block partial sums (FP64) of
-// g_l = s_l^T u_j, q_l = s_l^T s_j (l <= j) and c = r0^T s_j.  A row block covers
-// FU_CHUNKS chunks of FU_ROWS rows; each chunk stages its action rows in LDS with all
-// loads in flight at once.  Layout of one block's partials: [g (imax) | q (imax) | c].
-// The TT_COLS-wide column blocks after the row blocks compute (T^T t_j)_l = t_l^T t_j
-// for l <= j (FP64), one wave per column group.
+// u_j[p] = sigma_f2 * (sum over the nb slots of the tile partial sums, FP64), stored in
+// U[:, j], and per-block partial sums (FP64) of s_j^T u_j, FU_ROWS rows per block.  The
+// TT_COLS-wide column blocks after the row blocks compute (T^T t_j)_l = t_l^T t_j for
+// l <= j (FP64), one wave per column group.
 constexpr int FU_ROWS = 64;
-constexpr int FU_CHUNKS = 2;
 constexpr int TT_COLS = 16;
 
 __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
                                                 const float* __restrict__ S,
                                                 float* __restrict__ U,
-                                                const float* __restrict__ r0,
                                                 const float* __restrict__ T, ObsDims d,
                                                 int j, double sigma_f2, int n_rowblk,
-                                                double* __restrict__ gpart,
+                                                double* __restrict__ fupart,
                                                 double* __restrict__ ttv,
                                                 const LoopState* __restrict__ ls) {
     if (ls->stop) return;
@@ -296,124 +336,83 @@ __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
         }
         return;
     }
-    __shared__ float Ss[FU_ROWS][257];
     __shared__ double ured[4][FU_ROWS];
-    __shared__ float uu[FU_ROWS], ss[FU_ROWS], rr[FU_ROWS];
     const int nb = d.mp / SYM_TILE;
-    double g = 0.0, q = 0.0, cc = 0.0;
-    for (int chunk = 0; chunk < FU_CHUNKS; ++chunk) {
-        const int p0 = (blockIdx.x * FU_CHUNKS + chunk) * FU_ROWS;
-        if (p0 >= d.m) break;
-        {
-            const int row = tid & 63, grp = tid >> 6;
-            const int p = p0 + row;
-            double a8[8];
+    const int row = tid & 63, grp = tid >> 6;
+    const int p = blockIdx.x * FU_ROWS + row;
+    double a8[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a8[u] = 0.0;
-            if (p < d.m) {
-                int s = grp;
-                for (; s + 28 < nb; s += 32) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) a8[u] += part[(size_t)(s + 4 * u) * d.mp + p];
-                }
-                for (; s < nb; s += 4) a8[0] += part[(size_t)s * d.mp + p];
-            }
-            ured[grp][row] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-        }
-        const int total = FU_ROWS * J;
-        for (int e0 = 0; e0 < total; e0 += 256 * 8) {
+    for (int u = 0; u < 8; ++u) a8[u] = 0.0;
+    float sj = 0.0f;
+    if (p < d.m) {
+        if (grp == 0) sj = S[(size_t)p * d.imax + j];
+        int sl = grp;
+        for (; sl + 28 < nb; sl += 32) {
             float v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + 256 * u + tid;
-                v[u] = 0.0f;
-                if (e < total) {
-                    const int row = e / J, col = e - row * J;
-                    const int p = p0 + row;
-                    if (p < d.m) v[u] = S[(size_t)p * d.imax + col];
-                }
-            }
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(sl + 4 * u) * d.mp + p];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + 256 * u + tid;
-                if (e < total) {
-                    const int row = e / J, col = e - row * J;
-                    Ss[row][col] = v[u];
-                }
-            }
+            for (int u = 0; u < 8; ++u) a8[u] += (double)v[u];
         }
-        __syncthreads();
-        if (tid < FU_ROWS) {
-            const int p = p0 + tid;
-            float uf = (float)(sigma_f2 * ((ured[0][tid] + ured[1][tid]) + (ured[2][tid] + ured[3][tid])));
-            float rv = 0.0f;
-            if (p < d.m) {
-                U[(size_t)p * d.imax + j] = uf;
-                rv = r0[p];
-            } else {
-                uf = 0.0f;
-            }
-            uu[tid] = uf;
-            ss[tid] = Ss[tid][j];
-            rr[tid] = rv;
-        }
-        __syncthreads();
-        if (tid < J) {
-#pragma unroll 8
-            for (int row = 0; row < FU_ROWS; ++row) {
-                const double sl = (double)Ss[row][tid];
-                g = __builtin_fma(sl, (double)uu[row], g);
-                q = __builtin_fma(sl, (double)ss[row], q);
-            }
-        }
-        if (tid >= 192) {
-            const int row = tid - 192;
-            cc = __builtin_fma((double)rr[row], (double)ss[row], cc);
-        }
-        __syncthreads();
+        for (; sl < nb; sl += 4) a8[0] += part[(size_t)sl * d.mp + p];
     }
-    const int gs = 2 * d.imax + 1;
-    double* out = gpart + (size_t)blockIdx.x * gs;
-    if (tid < J) {
-        out[tid] = g;
-        out[d.imax + tid] = q;
-    }
-    if (tid >= 192) {
-        cc = wave_sum(cc);
-        if (tid == 192) out[2 * d.imax] = cc;
+    ured[grp][row] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+    __syncthreads();
+    if (grp == 0) {
+        double prod = 0.0;
+        if (p < d.m) {
+            const float uf = (float)(sigma_f2 * ((ured[0][row] + ured[1][row]) +
+                                                 (ured[2][row] + ured[3][row])));
+            U[(size_t)p * d.imax + j] = uf;
+            prod = (double)sj * (double)uf;
+        }
+        prod = wave_sum(prod);
+        if (row == 0) fupart[blockIdx.x] = prod;
     }
 }
 
-void launch_form_u(const float* part, const float* S, float* U, const float* r0,
-                   const float* T, const ObsDims& d, int j, double sigma_f2, double* gpart,
-                   double* ttv, const LoopState* ls, hipStream_t st, int* nblk_out) {
-    const int rowblk = (d.m + FU_ROWS * FU_CHUNKS - 1) / (FU_ROWS * FU_CHUNKS);
+void launch_form_u(const float* part, const float* S, float* U, const float* T,
+                   const ObsDims& d, int j, double sigma_f2, double* fupart, double* ttv,
+                   const LoopState* ls, hipStream_t st, int* nblk_out) {
+    const int rowblk = (d.m + FU_ROWS - 1) / FU_ROWS;
     const int ttblk = d.rank > 0 ? (j + 1 + TT_COLS - 1) / TT_COLS : 0;
     *nblk_out = rowblk;
-    hipLaunchKernelGGL(k_form_u, dim3(rowblk + ttblk), dim3(256), 0, st, part, S, U, r0, T, d,
-                       j, sigma_f2, rowblk, gpart, ttv, ls);
+    hipLaunchKernelGGL(k_form_u, dim3(rowblk + ttblk), dim3(256), 0, st, part, S, U, T, d, j,
+                       sigma_f2, rowblk, fupart, ttv, ls);
 }
 
 // --------------------------------------------------------------------------- tail
-// One block of 1024 threads, FP64.  Finishes column j of C = S^T Ghat S, extends its
-// Cholesky factor C = L L^T (L^{-1} kept explicitly, row-major Linv and column-major
-// LinvT so that every triangular product reads coalesced), alpha = L^{-1} S^T r0,
-// beta = L^{-T} alpha, the Cholesky factor of S^T S (log det only) and the
-// log-likelihood term.  Every reduction and triangular product splits its terms over
-// several threads of a row and combines them with lane shuffles.  Stops the loop on
-// breakdown (pivot) or residual tolerance.
+// One block of 1024 threads, FP64.  Assembles column j of C = S^T Ghat S from the
+// column products, extends its Cholesky factor C = L L^T (L^{-1} kept explicitly,
+// row-major Linv and column-major LinvT so that every triangular product reads
+// coalesced), alpha = L^{-1} S^T r0, beta = L^{-T} alpha (updated in place: the new row
+// of L^{-1} times alpha_j is all that changes), the Cholesky factor of S^T S (log det
+// only) and the log-likelihood term.  Each triangular product splits a row over tpr
+// threads, issues its loads TAIL_BATCH at a time and combines the threads with lane
+// shuffles.  Stops the loop on breakdown (pivot) or residual tolerance.
 constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_BATCH = 8;      // loads in flight per thread in the triangular products
 
-__device__ __forceinline__ double tail_block_sum(double v, double* red) {
+// sums of three values over the block (same result in every thread)
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double (*red)[16]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v = wave_sum(v);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
     __syncthreads();
-    if (lane == 0) red[w] = v;
+    if (lane == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+        red[2][w] = c;
+    }
     __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < TAIL_THREADS / 64; ++k) s += red[k];
-    return s;
+    a = b = c = 0.0;
+#pragma unroll 2
+    for (int k = 0; k < TAIL_THREADS / 64; ++k) {
+        a += red[0][k];
+        b += red[1][k];
+        c += red[2][k];
+    }
 }
 
 // sum of v over groups of tpr consecutive lanes (tpr a power of two <= 64)
@@ -428,8 +427,9 @@ __device__ __forceinline__ int pow2_at_least(int v) {
     return p;
 }
 
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict__ gpart,
-                                                       int nblk,
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict__ colvec,
+                                                       const double* __restrict__ fupart,
+                                                       int nfu,
                                                        const double* __restrict__ ttv,
                                                        ObsDims d, int j, double noise_var,
                                                        double resid_tol, double pivot_tol,
@@ -442,43 +442,30 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
                                                        double* __restrict__ beta,
                                                        LoopState* __restrict__ ls) {
     __shared__ double Ccol[256], Qcol[256], lrow[256], lsrow[256], nrow[256], alph[256];
-    __shared__ double red[TAIL_THREADS / 64];
+    __shared__ double red[3][TAIL_THREADS / 64];
     const int tid = threadIdx.x;
     if (ls->stop) return;
-    const int gs = 2 * d.imax + 1;
     const int ld = d.imax;
     const int J = j + 1;
-    // 1. column j of S^T U and S^T S: pairs (array, l), tpp threads per pair
-    {
-        const int np = pow2_at_least(2 * J);
-        const int tpp = TAIL_THREADS / np >= 64 ? 64 : TAIL_THREADS / np;
-        const int pair = tid / tpp, sub = tid % tpp;
-        double acc = 0.0;
-        const bool live = pair < 2 * J;
-        if (live) {
-            const int off = pair < J ? pair : d.imax + (pair - J);
-            double a4[4] = {0.0, 0.0, 0.0, 0.0};
-            int b = sub;
-            for (; b + 3 * tpp < nblk; b += 4 * tpp) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) a4[u] += gpart[(size_t)(b + u * tpp) * gs + off];
-            }
-            for (; b < nblk; b += tpp) a4[0] += gpart[(size_t)b * gs + off];
-            acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-        }
-        acc = group_sum(acc, tpp);
-        if (live && sub == 0) {
-            if (pair < J) Ccol[pair] = acc;
-            else Qcol[pair - J] = acc;
-        }
-    }
-    double cpart = 0.0;
-    for (int b = tid; b < nblk; b += TAIL_THREADS) cpart += gpart[(size_t)b * gs + 2 * d.imax];
-    const double c_j = tail_block_sum(cpart, red);        // includes __syncthreads
+    // 1. column j: u_l^T s_j (l < j) and s_l^T s_j (l <= j) from the column products,
+    //    s_j^T u_j from form_u's partial sums
+    double fu = 0.0, cj = 0.0, unused = 0.0;
+    for (int b = tid; b < nfu; b += TAIL_THREADS) fu += fupart[b];
+    if (tid == 0) cj = colvec[2 * j + 1];
+    double gcol = 0.0, qcol = 0.0, tt = 0.0, al = 0.0;
     if (tid < J) {
-        const double tt = d.rank > 0 ? ttv[tid] : 0.0;
-        Ccol[tid] = Ccol[tid] - tt + noise_var * Qcol[tid];
-        alph[tid] = (tid < j) ? alpha[tid] : 0.0;
+        gcol = tid < j ? colvec[tid] : 0.0;
+        qcol = colvec[j + tid];
+        tt = d.rank > 0 ? ttv[tid] : 0.0;
+        al = tid < j ? alpha[tid] : 0.0;
+    }
+    block_sum3(fu, cj, unused, red);
+    const double c_j = cj;
+    if (tid < J) {
+        const double g = tid < j ? gcol : fu;
+        Ccol[tid] = g - tt + noise_var * qcol;
+        Qcol[tid] = qcol;
+        alph[tid] = al;
     }
     __syncthreads();
     if (j == 0) {
@@ -487,16 +474,29 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
         if (tid == 0) ls->stop = 1;
         return;
     }
-    // rows per triangular product: j (or J) rows, tpr threads per row
-    const int tpr = j > 0 ? std::min(64, TAIL_THREADS / pow2_at_least(J)) : 1;
+    // rows of the triangular products: j rows, tpr threads per row
+    const int tpr = j > 0 ? std::min(64, TAIL_THREADS / pow2_at_least(j)) : 1;
     const int row = tid / tpr, sub = tid % tpr;
     // 2. l = L^{-1} C[0:j, j] and ls = LS^{-1} Q[0:j, j]
     {
         double lk = 0.0, lsk = 0.0;
         if (row < j) {
-            for (int p = sub; p <= row; p += tpr) {
-                lk = __builtin_fma(LinvT[(size_t)p * ld + row], Ccol[p], lk);
-                lsk = __builtin_fma(LSinvT[(size_t)p * ld + row], Qcol[p], lsk);
+            for (int p0 = sub; p0 <= row; p0 += TAIL_BATCH * tpr) {
+                double a[TAIL_BATCH], b[TAIL_BATCH];
+#pragma unroll
+                for (int u = 0; u < TAIL_BATCH; ++u) {
+                    const int p = p0 + u * tpr;
+                    a[u] = p <= row ? LinvT[(size_t)p * ld + row] : 0.0;
+                    b[u] = p <= row ? LSinvT[(size_t)p * ld + row] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < TAIL_BATCH; ++u) {
+                    const int p = p0 + u * tpr;
+                    if (p <= row) {
+                        lk = __builtin_fma(a[u], Ccol[p], lk);
+                        lsk = __builtin_fma(b[u], Qcol[p], lsk);
+                    }
+                }
             }
         }
         lk = group_sum(lk, tpr);
@@ -507,15 +507,13 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
         }
     }
     __syncthreads();
-    double v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    double l2 = 0.0, ls2 = 0.0, la = 0.0;
     if (tid < j) {
-        v1 = lrow[tid] * lrow[tid];
-        v2 = lsrow[tid] * lsrow[tid];
-        v3 = lrow[tid] * alph[tid];
+        l2 = lrow[tid] * lrow[tid];
+        ls2 = lsrow[tid] * lsrow[tid];
+        la = lrow[tid] * alph[tid];
     }
-    const double l2 = tail_block_sum(v1, red);
-    const double ls2 = tail_block_sum(v2, red);
-    const double la = tail_block_sum(v3, red);
+    block_sum3(l2, ls2, la, red);
     const double d2 = Ccol[j] - l2;
     const bool finite = isfinite(d2) && isfinite(Ccol[j]);
     if (!(finite && d2 > pivot_tol * Ccol[j] && d2 > 0.0)) {
@@ -534,9 +532,22 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
     {
         double acc = 0.0, accs = 0.0;
         if (row < j) {
-            for (int k = row + sub; k < j; k += tpr) {
-                acc = __builtin_fma(lrow[k], Linv[(size_t)k * ld + row], acc);
-                accs = __builtin_fma(lsrow[k], LSinv[(size_t)k * ld + row], accs);
+            for (int k0 = row + sub; k0 < j; k0 += TAIL_BATCH * tpr) {
+                double a[TAIL_BATCH], b[TAIL_BATCH];
+#pragma unroll
+                for (int u = 0; u < TAIL_BATCH; ++u) {
+                    const int k = k0 + u * tpr;
+                    a[u] = k < j ? Linv[(size_t)k * ld + row] : 0.0;
+                    b[u] = k < j ? LSinv[(size_t)k * ld + row] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < TAIL_BATCH; ++u) {
+                    const int k = k0 + u * tpr;
+                    if (k < j) {
+                        acc = __builtin_fma(lrow[k], a[u], acc);
+                        accs = __builtin_fma(lsrow[k], b[u], accs);
+                    }
+                }
             }
         }
         acc = group_sum(acc, tpr);
@@ -558,7 +569,6 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
         LSinvT[(size_t)j * ld + j] = 1.0 / ds;
         L[(size_t)j * ld + j] = dj;
         nrow[j] = inv_d;
-        alph[j] = aj;
         alpha[j] = aj;
         ls->logdet_c += 2.0 * log(dj);
         ls->logdet_s += 2.0 * log(ds);
@@ -568,39 +578,34 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
                              ls->alpha2);
     }
     __syncthreads();
-    // 4. beta = L^{-T} alpha over the kept actions (row j of L^{-1} from LDS)
-    {
-        const int tprb = std::min(64, TAIL_THREADS / pow2_at_least(J));
-        const int rb = tid / tprb, sb = tid % tprb;
-        double acc = 0.0;
-        if (rb < J) {
-            for (int k = rb + sb; k < j; k += tprb)
-                acc = __builtin_fma(Linv[(size_t)k * ld + rb], alph[k], acc);
-        }
-        acc = group_sum(acc, tprb);
-        if (rb < J && sb == 0) beta[rb] = acc + nrow[rb] * alph[j];
+    // 4. beta = L^{-T} alpha: the previous beta plus alpha_j times row j of L^{-1}
+    if (tid < J) {
+        const double prev = tid < j ? beta[tid] : 0.0;
+        beta[tid] = __builtin_fma(aj, nrow[tid], prev);
     }
 }
 
-void launch_tail(const double* gpart, int nblk, const double* ttv, const ObsDims& d, int j,
-                 double noise_var, double resid_tol, double pivot_tol, double* Linv,
-                 double* LinvT, double* L, double* LSinv, double* LSinvT, double* alpha,
-                 double* beta, LoopState* ls, hipStream_t st) {
-    hipLaunchKernelGGL(k_tail, dim3(1), dim3(TAIL_THREADS), 0, st, gpart, nblk, ttv, d, j,
-                       noise_var, resid_tol, pivot_tol, Linv, LinvT, L, LSinv, LSinvT, alpha,
+void launch_tail(const double* colvec, const double* fupart, int nfu, const double* ttv,
+                 const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
+                 double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
+                 double* alpha, double* beta, LoopState* ls, hipStream_t st) {
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(TAIL_THREADS), 0, st, colvec, fupart, nfu, ttv, d,
+                       j, noise_var, resid_tol, pivot_tol, Linv, LinvT, L, LSinv, LSinvT, alpha,
                        beta, ls);
 }
 
 // ---------------------------------------------------------------------- next_action
-// CG policy: s_{j+1} = r0 - Ghat S beta = r0 - (U - Mo T + noise_var S) beta (the
-// residual after j+1 actions), stored unnormalised in S[:, j+1].  The low-rank part is
-// kept per row as V = Mo T: this launch adds column j, V[:, j] = Mo t_j, from the same
-// pass over the rows of Mo that also forms the per-block partial sums of Mo^T s_{j+1}
-// (finished by the next sym_tiles launch).  One wave per row, lanes over the action and
-// factor columns, NA_ROWS rows per wave loaded NA_BATCH at a time.
-constexpr int NA_ROWS = 16;
-constexpr int NA_BATCH = 4;
-
+// Produces (RESID: the CG policy) or reads (given actions, and s_0) action s_jt, and forms
+// the per-block partial sums (FP64) of its column products
+//     u_l^T s_jt (l < jt),  s_l^T s_jt (l <= jt),  r0^T s_jt,
+// laid out as [u^T s (jt) | s^T s (jt + 1) | r0^T s] in cpart[block * gs + pos].
+// RESID, with j = jt - 1: s_jt = r0 - Ghat S beta = r0 - (U - Mo T + noise_var S) beta,
+// the residual after jt actions, stored unnormalised in S[:, jt]; V[:, j] = Mo t_j (the
+// low-rank part kept per row, V = Mo T) and the per-block partial sums of Mo^T s_jt
+// (finished by the next sym_tiles launch) come from the same pass over the rows of Mo.
+// Each wave takes RW rows with all their loads in flight at once; lanes own CPL
+// consecutive factor columns and the action columns lane + 64 v, v < LPL.
+template <bool RESID, int CPL, int LPL, int RW>
 __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U,
                                                      const float* __restrict__ Mo,
                                                      const float* __restrict__ r0,
@@ -608,91 +613,187 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
                                                      float* __restrict__ V,
                                                      const double* __restrict__ beta,
                                                      const float* __restrict__ T,
-                                                     float noise_var, ObsDims d, int j,
+                                                     float noise_var, ObsDims d, int jt,
                                                      float* __restrict__ mpart,
+                                                     double* __restrict__ cpart, int gs,
                                                      const LoopState* __restrict__ ls) {
     if (ls->stop) return;
-    __shared__ float red[4][1024];
+    __shared__ float mred[RESID ? 4 : 1][RESID ? 64 * CPL : 1];
+    __shared__ double gred[4][64 * LPL], qred[4][64 * LPL];
+    __shared__ double sred[2][4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int p0 = (blockIdx.x * 4 + w) * NA_ROWS;
-    float bl[4], tj[16], acc[16];
+    const int p0 = (blockIdx.x * 4 + w) * RW;
+    const int j = jt - 1;
+    const bool lowrank = RESID && d.rank > 0;
+    float tj[CPL], acc[CPL], bl[LPL];
+    double g[LPL], q[LPL];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int k = 0; k < CPL; ++k) {
+        const int c = lane * CPL + k;
+        tj[k] = (lowrank && c < d.rank) ? T[(size_t)j * d.ldmo + c] : 0.0f;
+        acc[k] = 0.0f;
+    }
+#pragma unroll
+    for (int v = 0; v < LPL; ++v) {
         const int l = lane + 64 * v;
-        bl[v] = (l <= j) ? (float)beta[l] : 0.0f;
+        bl[v] = (RESID && l <= j) ? (float)beta[l] : 0.0f;
+        g[v] = 0.0;
+        q[v] = 0.0;
     }
-    const float* tcol = T + (size_t)j * d.ldmo;
+    const float bj = RESID ? (float)beta[j] : 0.0f;
+    // loads of all RW rows
+    float mo[RW][CPL], uu[RW][LPL], sv[RW][LPL], vv[RW][LPL], r0v[RW], sr[RW];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int c = lane + 64 * u;
-        tj[u] = (c < d.rank) ? tcol[c] : 0.0f;
-        acc[u] = 0.0f;
+    for (int b = 0; b < RW; ++b) {
+        const int p = min(p0 + b, d.m - 1);
+        r0v[b] = r0[p];
+        sr[b] = RESID ? 0.0f : S[(size_t)p * d.imax + jt];
+#pragma unroll
+        for (int v = 0; v < LPL; ++v) {
+            const int l = lane + 64 * v;
+            uu[b][v] = l < jt ? U[(size_t)p * d.imax + l] : 0.0f;
+            sv[b][v] = l < jt ? S[(size_t)p * d.imax + l] : 0.0f;
+            vv[b][v] = (RESID && l < j) ? V[(size_t)p * d.imax + l] : 0.0f;
+        }
+#pragma unroll
+        for (int k4 = 0; k4 < CPL / 4; ++k4) {
+            const int c = lane * CPL + 4 * k4;
+            float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (lowrank && c < d.ldmo)
+                x = *reinterpret_cast<const float4*>(Mo + (size_t)p * d.ldmo + c);
+            mo[b][4 * k4] = x.x;
+            mo[b][4 * k4 + 1] = x.y;
+            mo[b][4 * k4 + 2] = x.z;
+            mo[b][4 * k4 + 3] = x.w;
+        }
     }
-    const int rows = min(NA_ROWS, d.m - p0);
-    for (int rr = 0; rr < rows; rr += NA_BATCH) {
-        float mo[NA_BATCH][16], part[NA_BATCH], vj[NA_BATCH];
+    float rho[RW];
+    if constexpr (RESID) {
+        float dotp[RW], part[RW];
 #pragma unroll
-        for (int b = 0; b < NA_BATCH; ++b) {
-            const int p = p0 + min(rr + b, rows - 1);
-            const float* Mrow = Mo + (size_t)p * d.ldmo;
-            vj[b] = 0.0f;
+        for (int b = 0; b < RW; ++b) {
+            dotp[b] = 0.0f;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int c = lane + 64 * u;
-                mo[b][u] = (c < d.rank) ? Mrow[c] : 0.0f;
-                vj[b] = __builtin_fmaf(mo[b][u], tj[u], vj[b]);
-            }
-            const float* Urow = U + (size_t)p * d.imax;
-            const float* Srow = S + (size_t)p * d.imax;
-            const float* Vrow = V + (size_t)p * d.imax;
+            for (int k = 0; k < CPL; ++k) dotp[b] = __builtin_fmaf(mo[b][k], tj[k], dotp[b]);
             part[b] = 0.0f;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int l = lane + 64 * v;
-                if (l < j)
-                    part[b] -= (__builtin_fmaf(noise_var, Srow[l], Urow[l]) - Vrow[l]) * bl[v];
-                else if (l == j)
-                    part[b] -= __builtin_fmaf(noise_var, Srow[l], Urow[l]) * bl[v];
-            }
+            for (int v = 0; v < LPL; ++v)
+                part[b] = __builtin_fmaf(vv[b][v] - __builtin_fmaf(noise_var, sv[b][v], uu[b][v]),
+                                         bl[v], part[b]);
         }
 #pragma unroll
-        for (int b = 0; b < NA_BATCH; ++b) {
-            const bool live = rr + b < rows;
-            const int p = p0 + rr + b;
-            const float vpj = wave_sum(vj[b]);
-            // the V[:, j] term of row p, held by the lane that owns column j
-            const int lj = j & 63, vj_slot = j >> 6;
-            float extra = 0.0f;
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                if (v == vj_slot && lane == lj) extra = vpj * bl[v];
-            const float rho = live ? r0[p] + wave_sum(part[b] + extra) : 0.0f;
-            if (live && lane == 0) {
-                S[(size_t)p * d.imax + j + 1] = rho;
-                V[(size_t)p * d.imax + j] = vpj;
+        for (int b = 0; b < RW; ++b) {
+            const float vs = wave_sum(dotp[b]);
+            const float ps = wave_sum(part[b]);
+            const bool live = p0 + b < d.m;
+            rho[b] = live ? r0v[b] + ps + bj * vs : 0.0f;
+            if (live && lane == b) {
+                S[(size_t)(p0 + b) * d.imax + jt] = rho[b];
+                V[(size_t)(p0 + b) * d.imax + j] = vs;
             }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] = __builtin_fmaf(mo[b][u], rho, acc[u]);
         }
+    } else {
+#pragma unroll
+        for (int b = 0; b < RW; ++b) rho[b] = p0 + b < d.m ? sr[b] : 0.0f;
+    }
+    double qq = 0.0, cc = 0.0;
+#pragma unroll
+    for (int b = 0; b < RW; ++b) {
+        const double rd = rho[b];
+        if (lowrank) {
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) acc[k] = __builtin_fmaf(mo[b][k], rho[b], acc[k]);
+        }
+#pragma unroll
+        for (int v = 0; v < LPL; ++v) {
+            g[v] = __builtin_fma((double)uu[b][v], rd, g[v]);
+            q[v] = __builtin_fma((double)sv[b][v], rd, q[v]);
+        }
+        qq = __builtin_fma(rd, rd, qq);
+        cc = __builtin_fma((double)r0v[b], rd, cc);
+    }
+    // block sums over the 4 waves, fixed order
+    if (lowrank) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) mred[RESID ? w : 0][RESID ? lane * CPL + k : 0] = acc[k];
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int c = lane + 64 * u;
-        if (c < d.rank) red[w][c] = acc[u];
+    for (int v = 0; v < LPL; ++v) {
+        gred[w][lane + 64 * v] = g[v];
+        qred[w][lane + 64 * v] = q[v];
+    }
+    if (lane == 0) {
+        sred[0][w] = qq;
+        sred[1][w] = cc;
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < d.rank; c += 256)
-        mpart[(size_t)blockIdx.x * d.ldmo + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    if (lowrank) {
+        for (int c = threadIdx.x; c < d.rank; c += 256)
+            mpart[(size_t)blockIdx.x * d.ldmo + c] =
+                (mred[0][c] + mred[RESID ? 1 : 0][c]) + (mred[RESID ? 2 : 0][c] + mred[RESID ? 3 : 0][c]);
+    }
+    double* out = cpart + (size_t)blockIdx.x * gs;
+    for (int pos = threadIdx.x; pos < 2 * jt + 2; pos += 256) {
+        double v;
+        if (pos < jt) {
+            v = (gred[0][pos] + gred[1][pos]) + (gred[2][pos] + gred[3][pos]);
+        } else if (pos < 2 * jt) {
+            const int l = pos - jt;
+            v = (qred[0][l] + qred[1][l]) + (qred[2][l] + qred[3][l]);
+        } else {
+            const int k = pos - 2 * jt;
+            v = (sred[k][0] + sred[k][1]) + (sred[k][2] + sred[k][3]);
+        }
+        out[pos] = v;
+    }
 }
 
-void launch_next_action(const float* U, const float* Mo, const float* r0, float* S, float* V,
-                        const double* beta, const float* T, float noise_var,
-                        const ObsDims& d, int j, float* mpart, const LoopState* ls,
-                        hipStream_t st, int* nblk_out) {
-    const int blocks = (d.m + 4 * NA_ROWS - 1) / (4 * NA_ROWS);
+template <bool RESID, int CPL, int LPL>
+static void launch_na(int blocks, const float* U, const float* Mo, const float* r0, float* S,
+                      float* V, const double* beta, const float* T, float noise_var,
+                      const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
+                      const LoopState* ls, hipStream_t st) {
+    constexpr int RW = next_action_rows_per_wave(CPL, LPL);
+    hipLaunchKernelGGL((k_next_action<RESID, CPL, LPL, RW>), dim3(blocks), dim3(256), 0, st, U,
+                       Mo, r0, S, V, beta, T, noise_var, d, jt, mpart, cpart, gs, ls);
+}
+
+template <bool RESID, int CPL>
+static void launch_na_l(int lpl, int blocks, const float* U, const float* Mo, const float* r0,
+                        float* S, float* V, const double* beta, const float* T, float noise_var,
+                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
+                        const LoopState* ls, hipStream_t st) {
+    if (lpl == 1)
+        launch_na<RESID, CPL, 1>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
+                                 cpart, gs, ls, st);
+    else if (lpl == 2)
+        launch_na<RESID, CPL, 2>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
+                                 cpart, gs, ls, st);
+    else
+        launch_na<RESID, CPL, 4>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
+                                 cpart, gs, ls, st);
+}
+
+void launch_next_action(int resid, const float* U, const float* Mo, const float* r0, float* S,
+                        float* V, const double* beta, const float* T, float noise_var,
+                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
+                        const LoopState* ls, hipStream_t st, int* nblk_out) {
+    const int lpl = next_action_lpl(d.imax);
+    const int cpl = resid ? next_action_cpl(d.ldmo) : 4;
+    const int blocks = next_action_blocks(d.m, cpl, lpl);
     *nblk_out = blocks;
-    hipLaunchKernelGGL(k_next_action, dim3(blocks), dim3(256), 0, st, U, Mo, r0, S, V, beta, T,
-                       noise_var, d, j, mpart, ls);
+    if (!resid)
+        launch_na_l<false, 4>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
+                              cpart, gs, ls, st);
+    else if (cpl == 4)
+        launch_na_l<true, 4>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
+                             cpart, gs, ls, st);
+    else if (cpl == 8)
+        launch_na_l<true, 8>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
+                             cpart, gs, ls, st);
+    else
+        launch_na_l<true, 16>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
+                              cpart, gs, ls, st);
 }
 
 // ----------------------------------------------------------------------- build_block

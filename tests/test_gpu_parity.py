@@ -37,6 +37,7 @@ CASES = {
     "plane_m52": dict(dim=2, nu2=5, ell=0.2, n=500, m=190, i=12, r=30, T=5, noise_var=0.01),
     "sphere_m12_geodesic": dict(nu2=1, dist=1, n=700, m=257, i=6, r=14, T=5),
     "sphere_m32_geodesic": dict(dist=1, n=600, m=129, i=10, r=16, T=4),
+    "plane_m12": dict(dim=2, nu2=1, ell=0.25, n=450, m=200, i=8, r=18, T=4),
 }
 
 
