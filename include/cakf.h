@@ -93,6 +93,8 @@ typedef struct {
                                typical 1e-10                                         */
     int prec;               /* CAKF_PREC_* of the block product                      */
     int smoother;           /* nonzero: also allocate the smoother workspace         */
+    int gradient;           /* nonzero: also allocate the workspace of
+                               cakf_loglik_grad (needs max_actions <= 159)           */
     void* stream;           /* hipStream_t for all work; NULL = the null stream      */
 } cakf_config;
 
@@ -106,6 +108,7 @@ typedef struct {
                                observation coordinates (W = H^T W_obs)              */
     float*   w_obs;         /* m: S (S^T Ghat S)^{-1} S^T r0 (w = H^T w_obs)         */
     double*  chol;          /* i x i: lower Cholesky factor L of S^T Ghat S          */
+    double*  chol_inv;      /* i x i: L^{-1} (lower triangular)                      */
     double*  loglik;        /* 1: projected log-likelihood term of this step         */
     int*     n_actions;     /* 1: number of actions kept                             */
 } cakf_record;
@@ -211,6 +214,44 @@ int cakf_smooth_begin(cakf_ctx* ctx, const int32_t* idx, const float* w_obs,
  * output may be NULL.  P_k = Sigma - M_k M_k^T uses the untruncated filter factor. */
 int cakf_smooth_step(cakf_ctx* ctx, const cakf_smooth_input* in, float* mean_out,
                      float* factor_out, int ld_out, float* var_out, int* out_rank);
+
+/* One filter step as the derivative of the log-likelihood needs it: the step's inputs,
+ * its record and the state it passed on, all caller-owned device buffers written by the
+ * forward run (read only here).
+ *   idx, y, m     the observations of step k (m = 0: no data);
+ *   S, W_obs, w_obs, chol, chol_inv, n_actions   the step's cakf_record;
+ *   mean          m_k, the filter mean after step k (n);
+ *   factor        M_k^+, the factor after the truncation of step k (n x rank, row-major,
+ *                 leading dimension ld), i.e. the state the next step predicts from;
+ *   rotation      the V_r of the step's cakf_truncate (rank_full x rank, row-major FP64),
+ *                 or NULL when the step did not truncate (then rank = rank_full). */
+typedef struct {
+    const int32_t* idx;
+    const float* y;
+    int m;
+    const float* S;
+    const float* W_obs;
+    const float* w_obs;
+    const double* chol;
+    const double* chol_inv;
+    const int* n_actions;
+    const float* mean;
+    const float* factor;
+    int ld, rank;
+    const double* rotation;
+    int rank_full;
+} cakf_tape_step;
+
+/* Derivative of the log-likelihood of cakf_loglik over the T steps of tape (a run from
+ * the prior with this context's parameters) with respect to
+ *   grad[0] the spatial lengthscale, grad[1] the OU coefficient a,
+ *   grad[2] the signal variance,      grad[3] the noise variance,
+ * holding the actions and the truncation rotations fixed at their recorded values (the
+ * derivative of the filter as it was run).  Reverse sweep over the steps: kernel tiles
+ * are recomputed, nothing of size n x m is stored.  Needs cfg.gradient != 0, the
+ * context's max_actions <= 159 and distinct indices within each step.  grad: host,
+ * 4 doubles.  Synchronises the stream. */
+int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double* grad);
 
 /* Phases timed by the profiling hooks (HIP events on the context stream around each
  * launch of the phase). */

@@ -35,14 +35,15 @@ class cakf_config(ctypes.Structure):
         ("max_obs", ctypes.c_int), ("max_actions", ctypes.c_int), ("max_rank", ctypes.c_int),
         ("policy", ctypes.c_int), ("resid_tol", ctypes.c_double),
         ("pivot_tol", ctypes.c_double), ("prec", ctypes.c_int), ("smoother", ctypes.c_int),
-        ("stream", ctypes.c_void_p),
+        ("gradient", ctypes.c_int), ("stream", ctypes.c_void_p),
     ]
 
 
 class cakf_record(ctypes.Structure):
     _fields_ = [
         ("S", ctypes.c_void_p), ("W_obs", ctypes.c_void_p), ("w_obs", ctypes.c_void_p),
-        ("chol", ctypes.c_void_p), ("loglik", ctypes.c_void_p), ("n_actions", ctypes.c_void_p),
+        ("chol", ctypes.c_void_p), ("chol_inv", ctypes.c_void_p), ("loglik", ctypes.c_void_p),
+        ("n_actions", ctypes.c_void_p),
     ]
 
 
@@ -52,6 +53,17 @@ class cakf_smooth_input(ctypes.Structure):
         ("rank", ctypes.c_int), ("pred_factor", ctypes.c_void_p), ("pred_ld", ctypes.c_int),
         ("pred_rank", ctypes.c_int), ("idx", ctypes.c_void_p), ("w_obs", ctypes.c_void_p),
         ("W_obs", ctypes.c_void_p), ("m", ctypes.c_int),
+    ]
+
+
+class cakf_tape_step(ctypes.Structure):
+    _fields_ = [
+        ("idx", ctypes.c_void_p), ("y", ctypes.c_void_p), ("m", ctypes.c_int),
+        ("S", ctypes.c_void_p), ("W_obs", ctypes.c_void_p), ("w_obs", ctypes.c_void_p),
+        ("chol", ctypes.c_void_p), ("chol_inv", ctypes.c_void_p),
+        ("n_actions", ctypes.c_void_p), ("mean", ctypes.c_void_p),
+        ("factor", ctypes.c_void_p), ("ld", ctypes.c_int), ("rank", ctypes.c_int),
+        ("rotation", ctypes.c_void_p), ("rank_full", ctypes.c_int),
     ]
 
 
@@ -86,6 +98,8 @@ def lib() -> ctypes.CDLL:
             "cakf_smooth_begin": (i, [vp, vp, vp, vp, i]),
             "cakf_smooth_step": (i, [vp, ctypes.POINTER(cakf_smooth_input), vp, vp, i, vp,
                                      ctypes.POINTER(i)]),
+            "cakf_loglik_grad": (i, [vp, i, ctypes.POINTER(cakf_tape_step),
+                                     ctypes.POINTER(d)]),
             "cakf_profile_enable": (i, [vp, i]),
             "cakf_profile_read": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(i)]),
         }
@@ -207,3 +221,11 @@ def cakf_loglik(ctx: int):
     v, n = ctypes.c_double(), ctypes.c_int()
     check(lib().cakf_loglik(ctx, ctypes.byref(v), ctypes.byref(n)), "cakf_loglik")
     return v.value, n.value
+
+
+def cakf_loglik_grad(ctx: int, tape) -> list:
+    """tape: a sequence of cakf_tape_step; returns the 4 derivatives (host doubles)."""
+    arr = (cakf_tape_step * len(tape))(*tape)
+    g = (ctypes.c_double * 4)()
+    check(lib().cakf_loglik_grad(ctx, len(tape), arr, g), "cakf_loglik_grad")
+    return list(g)

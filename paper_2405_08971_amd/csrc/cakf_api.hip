@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 #include <new>
 
 #include "../../include/cakf.h"
@@ -91,6 +92,17 @@ struct cakf_ctx {
     bool sm_started;
     float *sm_B, *sm_Y, *sm_Z, *sm_Q, *sm_Gr, *sm_R, *sm_WR;
     __bf16 *sm_Bth, *sm_Btl;
+    // log-likelihood derivative (allocated when cfg.gradient != 0)
+    float* gMb[2];     // adjoint of the factor (n x ldM), ping-pong
+    float* gmb;        // adjoint of the mean (n)
+    float* gYb;        // adjoint of the new columns and the mean increment (n x bp)
+    float *gBq, *gBb;  // B = [W w] and its adjoint (mpmax x bp)
+    float* gbpart;     // per-slice partials of K(Xo, X) Ybar
+    size_t gbpart_elems;
+    double* gspart;    // per-block partial sums of the tile kernels
+    int gspart_blocks;
+    float *gQb, *gMob, *gZr, *gCc;
+    double *gW64, *gSr64, *gBb64, *gG1, *gG2, *gX1, *gX2, *gpart, *gacc;
 };
 
 namespace {
@@ -139,7 +151,10 @@ static void free_all(cakf_ctx* c) {
                     c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->Bth, c->Btl, c->G, c->gwork, c->eigval,
                     c->offdiag, c->info, c->Vr, c->blas_ws, c->Xp, c->sm_ws, c->sm_W[0],
                     c->sm_W[1], c->sm_B, c->sm_Y, c->sm_Z, c->sm_Q, c->sm_Gr, c->sm_R,
-                    c->sm_WR, c->sm_Bth, c->sm_Btl};
+                    c->sm_WR, c->sm_Bth, c->sm_Btl, c->gMb[0], c->gMb[1], c->gmb, c->gYb,
+                    c->gBq, c->gBb, c->gbpart, c->gspart, c->gQb, c->gMob, c->gZr, c->gCc,
+                    c->gW64, c->gSr64, c->gBb64, c->gG1, c->gG2, c->gX1, c->gX2, c->gpart,
+                    c->gacc};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -171,6 +186,7 @@ static int validate(const cakf_config* c) {
         return CAKF_E_ARG;
     if (c->resid_tol < 0 || c->pivot_tol < 0) return CAKF_E_ARG;
     if (c->smoother && (size_t)c->n * (c->max_rank + 1) > ((size_t)1 << 31)) return CAKF_E_ARG;
+    if (c->gradient && c->max_actions > 159) return CAKF_E_ARG;
     return CAKF_OK;
 }
 
@@ -257,6 +273,33 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         rc |= dalloc(&c->sm_WR, (size_t)c->mmax * c->bps);
         rc |= dalloc(&c->sm_Bth, (size_t)c->np * c->bps);
         rc |= dalloc(&c->sm_Btl, (size_t)c->np * c->bps);
+    }
+    if (cfg->gradient) {
+        const size_t I = c->imax, I1 = c->imax + 1;
+        rc |= dalloc(&c->gMb[0], n * c->ldM);
+        rc |= dalloc(&c->gMb[1], n * c->ldM);
+        rc |= dalloc(&c->gmb, n);
+        rc |= dalloc(&c->gYb, n * c->bp);
+        rc |= dalloc(&c->gBq, (size_t)c->mpmax * c->bp);
+        rc |= dalloc(&c->gBb, (size_t)c->mpmax * c->bp);
+        // slices x (m rounded to 32) <= 2048 x 32 + mpmax rows of partials
+        c->gbpart_elems = ((size_t)2048 * 32 + c->mpmax) * c->bp;
+        rc |= dalloc(&c->gbpart, c->gbpart_elems);
+        c->gspart_blocks = 2048 + c->mpmax / 32 + 1;
+        rc |= dalloc(&c->gspart, (size_t)2 * c->gspart_blocks);
+        rc |= dalloc(&c->gQb, (size_t)c->r * c->bp);
+        rc |= dalloc(&c->gMob, (size_t)c->mpmax * c->ldmo);
+        rc |= dalloc(&c->gZr, (size_t)c->mpmax * I1);
+        rc |= dalloc(&c->gCc, I * I1);
+        rc |= dalloc(&c->gW64, (size_t)c->mpmax * I);
+        rc |= dalloc(&c->gSr64, (size_t)c->mpmax * I1);
+        rc |= dalloc(&c->gBb64, (size_t)c->mpmax * I1);
+        rc |= dalloc(&c->gG1, I * I1);
+        rc |= dalloc(&c->gG2, I * I1);
+        rc |= dalloc(&c->gX1, I * I);
+        rc |= dalloc(&c->gX2, I * I);
+        rc |= dalloc(&c->gpart, (n + 3) / 4);
+        rc |= dalloc(&c->gacc, 4);
     }
     if (rc) {
         free_all(c);
@@ -375,7 +418,7 @@ __global__ void k_count_diag(const LoopState* ls, Diag* dg) {
 extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int m,
                            const float* actions, const cakf_record* rec) {
     if (!c || m < 0 || m > c->mmax) return CAKF_E_ARG;
-    const cakf_record none = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const cakf_record none = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (!rec) rec = &none;
     hipStream_t st = c->stream;
     if (m == 0) {
@@ -474,7 +517,8 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
                                c->ldM));
     }
     launch_mean_add(c->mean, M, c->n, c->ldM, d.rank + c->imax, st);
-    launch_finish_record(c->ls, c->L, c->imax, rec->chol, rec->loglik, rec->n_actions, st);
+    launch_finish_record(c->ls, c->L, c->Linv, c->imax, rec->chol, rec->chol_inv, rec->loglik,
+                         rec->n_actions, st);
     hipLaunchKernelGGL(k_count_diag, dim3(1), dim3(1), 0, st, c->ls, c->diag);
     c->rank += c->imax;
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
@@ -514,6 +558,151 @@ extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
     if (rc) return rc;
     c->cur = 1 - c->cur;
     c->rank = c->r;
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+
+// ------------------------------------------------------- log-likelihood derivative
+// Row-major GEMM C (M x N) = alpha op(A) op(B) + beta C through column-major rocBLAS
+// (a row-major matrix is its transpose in column-major storage).
+static rocblas_status sgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K,
+                               float alpha, const float* A, int lda, const float* B, int ldb,
+                               float beta, float* C, int ldc) {
+    return rocblas_sgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
+                         &alpha, B, ldb, A, lda, &beta, C, ldc);
+}
+
+static rocblas_status dgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K,
+                               double alpha, const double* A, int lda, const double* B,
+                               int ldb, double beta, double* C, int ldc) {
+    return rocblas_dgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
+                         &alpha, B, ldb, A, lda, &beta, C, ldc);
+}
+
+extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, double* grad) {
+    if (!c || !grad || T < 1 || !tape || !c->gMb[0]) return CAKF_E_ARG;
+    hipStream_t st = c->stream;
+    const int n = c->n, imax = c->imax, bp = c->bp, ldM = c->ldM, ldmo = c->ldmo;
+    const int I1 = imax + 1;
+    const double ell = c->cfg.lengthscale, s2 = c->cfg.signal_var;
+    const float a = (float)c->cfg.ou_coeff;
+    // host-side shapes of every step (ranks follow from the update and truncation rules)
+    std::vector<int> kept(T, 0);
+    for (int k = 0; k < T; ++k) {
+        const cakf_tape_step& t = tape[k];
+        if (t.m < 0 || t.m > c->mmax || !t.mean || !t.factor || t.rank < 0 ||
+            t.rank > c->r || (t.rank > 0 && t.ld < t.rank))
+            return CAKF_E_ARG;
+        if (t.m > 0 && (!t.idx || !t.y || !t.S || !t.W_obs || !t.w_obs || !t.chol ||
+                        !t.chol_inv || !t.n_actions))
+            return CAKF_E_ARG;
+        const int prev = k > 0 ? tape[k - 1].rank : 0;
+        const int full = t.m > 0 ? prev + imax : prev;
+        if (t.rotation ? (t.rank_full != full || t.rank > full) : t.rank != full)
+            return CAKF_E_ARG;
+        if (t.m > 0) HIP_TRY(hipMemcpyAsync(&kept[k], t.n_actions, sizeof(int),
+                                            hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemsetAsync(c->gacc, 0, 4 * sizeof(double), st));
+    HIP_TRY(hipMemsetAsync(c->gmb, 0, (size_t)n * sizeof(float), st));
+    HIP_TRY(hipMemsetAsync(c->gMb[0], 0, (size_t)n * ldM * sizeof(float), st));
+    int cur = 0;   // gMb[cur] holds the adjoint of the factor passed on by step k
+    const int nu2 = c->cfg.kernel, dist = c->cfg.dist;
+    for (int k = T - 1; k >= 0; --k) {
+        const cakf_tape_step& t = tape[k];
+        const int rank = k > 0 ? tape[k - 1].rank : 0;     // columns of M^+_{k-1}
+        const float* mprev = k > 0 ? tape[k - 1].mean : nullptr;
+        const float* Mprev = k > 0 ? tape[k - 1].factor : nullptr;
+        const int ldprev = k > 0 ? tape[k - 1].ld : 1;
+        // 1. truncation: Mbar_k = Mbar^+_k V_r^T
+        float* Mbk = c->gMb[cur];
+        if (t.rotation) {
+            const int K = t.rank_full;
+            launch_to_f32(t.rotation, (size_t)K * t.rank, c->Vr, st);
+            Mbk = c->gMb[1 - cur];
+            if (K > 0)
+                BLAS_TRY(sgemm_rm(c->blas, false, true, n, K, t.rank, 1.0f, c->gMb[cur], ldM,
+                                  c->Vr, t.rank, 0.0f, Mbk, ldM));
+            cur = 1 - cur;
+        }
+        const int J = t.m > 0 ? kept[k] : 0;
+        if (J > 0) {
+            const int m = t.m, mp = round_up(m, 32);
+            // 2. Ybar, B, Mo, r0 and the FP64 copies
+            launch_adj_pack_ybar(Mbk, ldM, rank, imax, c->gmb, n, c->gYb, bp, st);
+            launch_adj_obs_prep(c->Xs, n, t.idx, t.y, m, mp, a, mprev, Mprev, ldprev, rank,
+                                t.W_obs, t.w_obs, t.S, imax, bp, ldmo, c->Xo, c->Mo, c->gBq,
+                                c->gW64, c->gSr64, st);
+            // 3. Bbar = sigma_f2 K(Xo, X) Ybar and the kernel terms of Y
+            {
+                int gx, gy, rps, gx2, gy2, rps2;
+                adj_tiles_geometry(n, m, &gx, &gy, &rps);
+                adj_tiles_geometry(m, m, &gx2, &gy2, &rps2);
+                if ((size_t)gy * mp * bp > c->gbpart_elems || gx * gy > c->gspart_blocks ||
+                    gx2 * gy2 > c->gspart_blocks)
+                    return CAKF_E_ARG;
+            }
+            int nblk = 0;
+            const int ns = launch_adj_tiles(nu2, dist, true, c->Xs, n, c->gYb, bp, c->Xo, m,
+                                            c->gBq, bp, imax + 1, c->gbpart, bp,
+                                            (size_t)mp * bp, c->gspart, &nblk, st);
+            if (ns < 0 || (size_t)ns * mp * bp > c->gbpart_elems || nblk > c->gspart_blocks)
+                return CAKF_E_ARG;
+            launch_adj_bbar_reduce(c->gbpart, (size_t)mp * bp, bp, ns, m, mp, imax + 1,
+                                   (float)s2, c->gBb, bp, st);
+            launch_adj_scalars(c->gspart, nblk, 1.0, s2 / ell, c->gacc, 2, 0, st);
+            if (rank > 0) {
+                // Q = Mo^T B, T = Mo^T S, Qbar = -a M^+_{k-1}^T Ybar
+                BLAS_TRY(sgemm_rm(c->blas, true, false, rank, bp, m, 1.0f, c->Mo, ldmo, c->gBq,
+                                  bp, 0.0f, c->Q, bp));
+                BLAS_TRY(sgemm_rm(c->blas, true, false, rank, imax, m, 1.0f, c->Mo, ldmo, t.S,
+                                  imax, 0.0f, c->T, imax));
+                BLAS_TRY(sgemm_rm(c->blas, true, false, rank, bp, n, -a, Mprev, ldprev, c->gYb,
+                                  bp, 0.0f, c->gQb, bp));
+                // Mbar^- -= Ybar Q^T;  Bbar += Mo Qbar;  Mobar = B Qbar^T
+                BLAS_TRY(sgemm_rm(c->blas, false, true, n, rank, bp, -1.0f, c->gYb, bp, c->Q,
+                                  bp, 1.0f, Mbk, ldM));
+                BLAS_TRY(sgemm_rm(c->blas, false, false, m, bp, rank, 1.0f, c->Mo, ldmo,
+                                  c->gQb, bp, 1.0f, c->gBb, bp));
+                BLAS_TRY(sgemm_rm(c->blas, false, true, m, rank, bp, 1.0f, c->gBq, bp, c->gQb,
+                                  bp, 0.0f, c->gMob, ldmo));
+            }
+            // 4. the Cholesky form in FP64: G1 = W^T Bbar, G2 = S^T [S r0]
+            launch_to_f64(c->gBb, bp, m, I1, c->gBb64, I1, st);
+            BLAS_TRY(dgemm_rm(c->blas, true, false, imax, I1, m, 1.0, c->gW64, imax, c->gBb64,
+                              I1, 0.0, c->gG1, I1));
+            BLAS_TRY(dgemm_rm(c->blas, true, false, imax, I1, m, 1.0, c->gSr64, I1, c->gSr64,
+                              I1, 0.0, c->gG2, I1));
+            launch_adj_small(J, imax, c->gG1, c->gG2, t.chol, t.chol_inv, c->gX1, c->gX2,
+                             c->gCc, c->gacc, 3, st);
+            // 5. [Z rbar0] = S [Cbar cbar]; the kernel terms of C = S^T Ghat S
+            BLAS_TRY(sgemm_rm(c->blas, false, false, m, I1, imax, 1.0f, t.S, imax, c->gCc, I1,
+                              0.0f, c->gZr, I1));
+            int nblk2 = 0;
+            if (launch_adj_tiles(nu2, dist, false, c->Xo, m, c->gZr, I1, c->Xo, m, t.S, imax, J,
+                                 nullptr, 0, 0, c->gspart, &nblk2, st) < 0 ||
+                nblk2 > c->gspart_blocks)
+                return CAKF_E_ARG;
+            launch_adj_scalars(c->gspart, nblk2, 1.0, s2 / ell, c->gacc, 2, 0, st);
+            if (rank > 0)
+                BLAS_TRY(sgemm_rm(c->blas, false, true, m, rank, imax, -2.0f, c->gZr, I1, c->T,
+                                  imax, 1.0f, c->gMob, ldmo));
+            // 6. scatter Mobar and -rbar0 into the adjoints of M^-, m^-
+            launch_adj_scatter(t.idx, m, n, c->gMob, ldmo, rank, c->gZr, I1, imax, Mbk, ldM,
+                               c->gmb, st);
+        }
+        // 7. predict: d/da and the adjoints of step k-1 (Mbar^- lives in Mbk's first columns)
+        if (k > 0) {
+            const int nb = launch_adj_predict(c->gmb, mprev, Mbk, ldM, Mprev, ldprev, rank, n,
+                                              a, c->gpart, st);
+            launch_sum_into(c->gpart, nb, c->gacc, 1, st);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(grad, c->gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 

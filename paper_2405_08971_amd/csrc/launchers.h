@@ -78,8 +78,9 @@ void launch_next_action(int resid, const float* U, const float* Mo, const float*
 void launch_build_block(const float* S, const double* Linv, const double* beta,
                         const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
                         float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st);
-void launch_finish_record(const LoopState* ls, const double* L, int imax, double* rec_chol,
-                          double* rec_loglik, int* rec_n, hipStream_t st);
+void launch_finish_record(const LoopState* ls, const double* L, const double* Linv, int imax,
+                          double* rec_chol, double* rec_chol_inv, double* rec_loglik, int* rec_n,
+                          hipStream_t st);
 
 // ---- block_product.hip
 void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
@@ -106,5 +107,36 @@ void launch_smooth_messages(const float* Bs, int ldb, int n, const int32_t* idx,
                             const float* WR, int ldr, float* ws, float* Wc, int ldw,
                             hipStream_t st);
 void launch_pad_points(const float4* Xs, int n, int np, float4* Xp, hipStream_t st);
+
+// ---- adjoint.hip
+// launch shape of k_adj_tiles: gx blocks of 32 q-points x gy slices of rps p-points
+void adj_tiles_geometry(int np_, int mq, int* gx, int* gy, int* rps);
+int launch_adj_tiles(int nu2, int dist, bool bbar, const float4* Xp, int np_, const float* Yp,
+                     int ldy, const float4* Xq, int mq, const float* Bq, int ldb, int b,
+                     float* bpart, int ldbp, size_t slice_stride, double* spart,
+                     int* nblocks, hipStream_t st);
+void launch_adj_bbar_reduce(const float* bpart, size_t slice_stride, int ldbp, int ns, int m,
+                            int mp, int b, float scale, float* out, int ldo, hipStream_t st);
+void launch_adj_scalars(const double* spart, int nblk, double ck, double cd, double* grad,
+                        int ik, int id, hipStream_t st);
+void launch_adj_pack_ybar(const float* Mb, int ldM, int rank, int imax, const float* mb, int n,
+                          float* Yb, int bp, hipStream_t st);
+void launch_adj_obs_prep(const float4* Xs, int n, const int32_t* idx, const float* y, int m,
+                         int mp, float a, const float* mprev, const float* Mprev, int ldprev,
+                         int rank, const float* W_obs, const float* w_obs, const float* S,
+                         int imax, int bp, int ldmo, float4* Xo, float* Mo, float* Bq,
+                         double* W64, double* Sr64, hipStream_t st);
+void launch_to_f64(const float* A, int lda, int rows, int cols, double* out, int ldo,
+                   hipStream_t st);
+void launch_to_f32(const double* A, size_t total, float* out, hipStream_t st);
+void launch_adj_small(int J, int imax, const double* G1, const double* G2, const double* L,
+                      const double* Linv, double* X1, double* X2, float* Cc, double* grad,
+                      int inoise, hipStream_t st);
+void launch_adj_scatter(const int32_t* idx, int m, int n, const float* Mob, int ldmo, int rank,
+                        const float* Zr, int ldz, int imax, float* Mb, int ldM, float* mb,
+                        hipStream_t st);
+int launch_adj_predict(float* mb, const float* mprev, float* Mb, int ldM, const float* Mprev,
+                       int ldprev, int rank, int n, float a, double* part, hipStream_t st);
+void launch_sum_into(const double* part, int nblk, double* grad, int i, hipStream_t st);
 
 }  // namespace cakf

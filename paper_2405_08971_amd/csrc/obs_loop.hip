@@ -847,11 +847,13 @@ void launch_build_block(const float* S, const double* Linv, const double* beta,
 
 // Record outputs that live in the loop state.
 __global__ void k_finish_record(const LoopState* __restrict__ ls, const double* __restrict__ L,
-                                int imax, double* __restrict__ rec_chol,
+                                const double* __restrict__ Linv, int imax,
+                                double* __restrict__ rec_chol, double* __restrict__ rec_chol_inv,
                                 double* __restrict__ rec_loglik, int* __restrict__ rec_n) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (rec_chol) {
-        for (int e = tid; e < imax * imax; e += gridDim.x * blockDim.x) rec_chol[e] = L[e];
+    for (int e = tid; e < imax * imax; e += gridDim.x * blockDim.x) {
+        if (rec_chol) rec_chol[e] = L[e];
+        if (rec_chol_inv) rec_chol_inv[e] = Linv[e];
     }
     if (tid == 0) {
         if (rec_loglik) *rec_loglik = ls->loglik;
@@ -859,10 +861,11 @@ __global__ void k_finish_record(const LoopState* __restrict__ ls, const double* 
     }
 }
 
-void launch_finish_record(const LoopState* ls, const double* L, int imax, double* rec_chol,
-                          double* rec_loglik, int* rec_n, hipStream_t st) {
-    hipLaunchKernelGGL(k_finish_record, dim3(64), dim3(256), 0, st, ls, L, imax, rec_chol,
-                       rec_loglik, rec_n);
+void launch_finish_record(const LoopState* ls, const double* L, const double* Linv, int imax,
+                          double* rec_chol, double* rec_chol_inv, double* rec_loglik, int* rec_n,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_finish_record, dim3(64), dim3(256), 0, st, ls, L, Linv, imax, rec_chol,
+                       rec_chol_inv, rec_loglik, rec_n);
 }
 
 }  // namespace cakf

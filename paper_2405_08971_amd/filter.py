@@ -23,12 +23,14 @@ class Record:
         self.W_obs = torch.zeros((m, i), dtype=torch.float32, device=device)
         self.w_obs = torch.zeros((m,), dtype=torch.float32, device=device)
         self.chol = torch.zeros((i, i), dtype=torch.float64, device=device)
+        self.chol_inv = torch.zeros((i, i), dtype=torch.float64, device=device)
         self.loglik = torch.zeros((1,), dtype=torch.float64, device=device)
         self.n_actions = torch.zeros((1,), dtype=torch.int32, device=device)
 
     def c(self) -> L.cakf_record:
         return L.cakf_record(L.ptr(self.S), L.ptr(self.W_obs), L.ptr(self.w_obs),
-                             L.ptr(self.chol), L.ptr(self.loglik), L.ptr(self.n_actions))
+                             L.ptr(self.chol), L.ptr(self.chol_inv), L.ptr(self.loglik),
+                             L.ptr(self.n_actions))
 
 
 class CAKF:
@@ -38,7 +40,7 @@ class CAKF:
                  lengthscale: float, signal_var: float = 1.0, noise_var: float,
                  ou_coeff: float, max_obs: int, max_actions: int, max_rank: int,
                  policy: str = "cg", resid_tol: float = 0.0, pivot_tol: float = 1e-10,
-                 prec: str = "fp32", smoother: bool = False,
+                 prec: str = "fp32", smoother: bool = False, gradient: bool = False,
                  stream: Optional[torch.cuda.Stream] = None):
         if X.dtype != torch.float32 or X.dim() != 2:
             raise ValueError("X must be a float32 (n, dim) device tensor")
@@ -52,7 +54,8 @@ class CAKF:
             lengthscale=lengthscale, signal_var=signal_var, noise_var=noise_var,
             ou_coeff=ou_coeff, max_obs=max_obs, max_actions=max_actions, max_rank=max_rank,
             policy=L.POLICY[policy], resid_tol=resid_tol, pivot_tol=pivot_tol,
-            prec=L.PREC[prec], smoother=1 if smoother else 0, stream=L.stream_handle(stream))
+            prec=L.PREC[prec], smoother=1 if smoother else 0, gradient=1 if gradient else 0,
+            stream=L.stream_handle(stream))
         self._X = X
         self.ctx = L.cakf_create(cfg)
 
@@ -152,6 +155,11 @@ class CAKF:
             out_fac = torch.empty((self.n, ld), dtype=torch.float32, device="cuda")
         rank = L.cakf_smooth_step(self.ctx, inp, out_mean, out_fac, ld, out_var)
         return out_mean, out_var, (out_fac[:, :rank] if want_factor else None)
+
+    def loglik_grad(self, tape) -> list:
+        """d loglik / d(lengthscale, ou_coeff, signal_var, noise_var) over a recorded run
+        (a sequence of cakf_tape_step; see paper_2405_08971_amd.autograd)."""
+        return L.cakf_loglik_grad(self.ctx, tape)
 
     def profile(self, on: bool = True):
         L.cakf_profile_enable(self.ctx, on)

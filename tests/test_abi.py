@@ -43,7 +43,8 @@ def test_library_exports_every_declared_function():
 def test_binding_structs_follow_the_header():
     from paper_2405_08971_amd import _lib
     for cname, pyname in [("cakf_config", _lib.cakf_config), ("cakf_record", _lib.cakf_record),
-                          ("cakf_smooth_input", _lib.cakf_smooth_input)]:
+                          ("cakf_smooth_input", _lib.cakf_smooth_input),
+                          ("cakf_tape_step", _lib.cakf_tape_step)]:
         assert [f[0] for f in pyname._fields_] == header_struct_fields(cname), cname
 
 
