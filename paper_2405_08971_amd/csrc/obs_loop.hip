@@ -312,22 +312,31 @@ __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
     const int tid = threadIdx.x;
     const int J = j + 1;
     if ((int)blockIdx.x >= n_rowblk) {
-        // (T^T t_j)_l for l in this block's TT_COLS columns, 4 per wave
+        // (T^T t_j)_l for l in this block's TT_COLS columns, 4 per wave; the loads of a
+        // batch of 8 factor-column groups are issued before any product
         const int lane = tid & 63, w = tid >> 6;
         const int l0 = (blockIdx.x - n_rowblk) * TT_COLS + w * (TT_COLS / 4);
         const float* tj = T + (size_t)j * d.ldmo;
         double acc[TT_COLS / 4];
 #pragma unroll
         for (int u = 0; u < TT_COLS / 4; ++u) acc[u] = 0.0;
-        for (int c0 = 0; c0 < d.rank; c0 += 64) {
-            const int c = c0 + lane;
-            const float tv = c < d.rank ? tj[c] : 0.0f;
+        for (int c0 = 0; c0 < d.rank; c0 += 8 * 64) {
+            float tv[8], tl[TT_COLS / 4][8];
 #pragma unroll
-            for (int u = 0; u < TT_COLS / 4; ++u) {
-                const int l = l0 + u;
-                const float tl = (l < J && c < d.rank) ? T[(size_t)l * d.ldmo + c] : 0.0f;
-                acc[u] = __builtin_fma((double)tl, (double)tv, acc[u]);
+            for (int g = 0; g < 8; ++g) {
+                const int c = c0 + 64 * g + lane;
+                tv[g] = c < d.rank ? tj[c] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < TT_COLS / 4; ++u) {
+                    const int l = l0 + u;
+                    tl[u][g] = (l < J && c < d.rank) ? T[(size_t)l * d.ldmo + c] : 0.0f;
+                }
             }
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+#pragma unroll
+                for (int u = 0; u < TT_COLS / 4; ++u)
+                    acc[u] = __builtin_fma((double)tl[u][g], (double)tv[g], acc[u]);
         }
 #pragma unroll
         for (int u = 0; u < TT_COLS / 4; ++u) {
@@ -347,6 +356,13 @@ __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
     if (p < d.m) {
         if (grp == 0) sj = S[(size_t)p * d.imax + j];
         int sl = grp;
+        for (; sl + 60 < nb; sl += 64) {
+            float v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = part[(size_t)(sl + 4 * u) * d.mp + p];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) a8[u & 7] += (double)v[u];
+        }
         for (; sl + 28 < nb; sl += 32) {
             float v[8];
 #pragma unroll
