@@ -68,18 +68,22 @@ def make_filter(cfg, X, prec, policy="cg"):
                 policy=policy, prec=prec)
 
 
-def run(cfg, X, inputs, warmup, steps, prec):
-    """Warm-up steps, then the timed steps.  Every step writes its record (actions,
-    messages, Cholesky factor, log-likelihood term) into buffers allocated beforehand."""
+def run(cfg, X, inputs, warmup, steps, prec, breakdown=3):
+    """Warm-up steps, then the timed steps, then `breakdown` more steps with every phase
+    timed (untimed as a whole).  In the timed steps only the dominant kernel's launches
+    are bracketed by HIP events (each bracket costs a few microseconds on the stream).
+    Every step writes its record (actions, messages, Cholesky factors, log-likelihood
+    term) into buffers allocated beforehand."""
     import torch
     from paper_2405_08971_amd.filter import Record
 
     f = make_filter(cfg, X, prec)
-    recs = [Record(cfg.m, cfg.i) for _ in range(warmup + steps)]
+    nrec = warmup + steps + breakdown
+    recs = [Record(cfg.m, cfg.i) for _ in range(nrec)]
     for k in range(warmup):
         f.step(*inputs[k], record=recs[k])
     torch.cuda.synchronize()
-    f.profile(True)
+    f.profile(["sym_tiles"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
@@ -87,13 +91,20 @@ def run(cfg, X, inputs, warmup, steps, prec):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = f.profile_read()
-    f.profile(False)
     mean, _ = f.state()
     var = f.marginal_var()
+    phases = {}
+    if breakdown:
+        f.profile(True)
+        for k in range(warmup + steps, nrec):
+            f.step(*inputs[k], record=recs[k])
+        phases = {name: v[0] / breakdown for name, v in f.profile_read().items()}
+    f.profile(False)
     dropped, nonfinite, bad = f.diagnostics()
     f.close()
-    return dict(elapsed=elapsed, prof=prof, mean=mean.cpu().numpy(), var=var.cpu().numpy(),
-                dropped=dropped, nonfinite=nonfinite, recs=recs)
+    return dict(elapsed=elapsed, prof=prof, phases=phases, mean=mean.cpu().numpy(),
+                var=var.cpu().numpy(), dropped=dropped, nonfinite=nonfinite,
+                recs=recs[:warmup + steps])
 
 
 def replay(cfg, X, inputs, recs, prec):
@@ -102,8 +113,8 @@ def replay(cfg, X, inputs, recs, prec):
     CG actions of a run depend on every rounding before them."""
     import torch
     f = make_filter(cfg, X, prec, policy="given")
-    for k, (idx, y) in enumerate(inputs):
-        f.step(idx, y, recs[k].S)
+    for (idx, y), rec in zip(inputs, recs):
+        f.step(idx, y, rec.S)
     torch.cuda.synchronize()
     mean, _ = f.state()
     var = f.marginal_var()
@@ -205,7 +216,7 @@ def main():
     cfg = CONFIGS[args.config]
     wl = Workload(cfg, seed=args.seed)
     X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
-    nsteps = args.warmup + args.steps
+    nsteps = args.warmup + args.steps + 3
     inputs = device_inputs(wl, range(1, nsteps + 1))
     torch.cuda.synchronize()
 
@@ -219,8 +230,7 @@ def main():
     sym_avg = sym_ms / max(sym_n, 1) * 1e-3
     trans_per_launch = 2.0 * m * (m + 1) / 2.0          # 2 per unique symmetric entry
     achieved = trans_per_launch / sym_avg if sym_avg > 0 else 0.0
-    bp_ms, bp_n = res["prof"]["block_product"]
-    bp_avg = bp_ms / max(bp_n, 1) * 1e-3
+    bp_avg = res["phases"].get("block_product", 0.0) * 1e-3    # one launch per step
     b = cfg.i + 1
     mfma_flop = 2.0 * cfg.n * m * b
     line = {
@@ -246,7 +256,7 @@ def main():
                      "unit": "Ttrans/s", "frac": achieved / PEAK_TRANS,
                      "traffic": traffic_per_launch("sym_tiles"),
                      "avg_launch_us": sym_avg * 1e6, "launches": sym_n},
-        "phases_ms_per_step": {k: v[0] / args.steps for k, v in res["prof"].items()},
+        "phases_ms_per_step": res["phases"],
         "block_product": {"avg_launch_us": bp_avg * 1e6,
                           "mfma_frac_algorithmic": (mfma_flop / bp_avg / PEAK_BF16)
                           if bp_avg > 0 else None},
@@ -256,7 +266,7 @@ def main():
         line["fp32_plain"] = {
             "value": args.steps / fp32["elapsed"],
             "ms_per_step": fp32["elapsed"] / args.steps * 1e3,
-            "phases_ms_per_step": {k: v[0] / args.steps for k, v in fp32["prof"].items()},
+            "phases_ms_per_step": fp32["phases"],
         }
         # precision alone: the FP32-plain path replaying the headline run's actions
         mref, vref = replay(cfg, X, inputs, res["recs"], "fp32")

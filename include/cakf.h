@@ -268,10 +268,13 @@ int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double* g
 #define CAKF_PHASE_TRUNCATE     10   /* cakf_step: truncate                              */
 #define CAKF_PHASES             11
 
-/* Enable (on != 0, resets the counters) or disable per-phase timing.  Enabling creates
- * HIP events once (host-side objects, no device memory); at most 2048 launches per
- * phase are timed between reads. */
-int cakf_profile_enable(cakf_ctx* ctx, int on);
+/* Per-phase timing: phases is a bit mask (bit p times phase p; -1 = all phases, 0 =
+ * off).  Enabling resets the counters and creates HIP events once (host-side objects,
+ * no device memory); at most 2048 launches per phase are timed between reads.  Each
+ * timed launch is bracketed by two events on the stream, which adds a few
+ * microseconds per launch: time only the phases needed. */
+#define CAKF_PROFILE_ALL (-1)
+int cakf_profile_enable(cakf_ctx* ctx, int phases);
 
 /* Total milliseconds and number of timed launches per phase since the last enable or
  * read (arrays of CAKF_PHASES entries), then reset the counters.  Synchronises the

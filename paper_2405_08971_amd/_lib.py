@@ -192,8 +192,8 @@ def cakf_diagnostics(ctx: int):
     return dr.value, nf.value, bi.value
 
 
-def cakf_profile_enable(ctx: int, on: bool) -> None:
-    check(lib().cakf_profile_enable(ctx, 1 if on else 0), "cakf_profile_enable")
+def cakf_profile_enable(ctx: int, on: int) -> None:
+    check(lib().cakf_profile_enable(ctx, int(on)), "cakf_profile_enable")
 
 
 def cakf_profile_read(ctx: int):

@@ -33,6 +33,7 @@ struct Prof {
     static constexpr int CAP = 2048;
     hipEvent_t* ev[CAKF_PHASES][2];
     int count[CAKF_PHASES];
+    int mask;           // bit p: phase p is timed
     bool on;
 };
 
@@ -111,11 +112,11 @@ struct PhaseTimer {
     cakf_ctx* c;
     int ph;
     PhaseTimer(cakf_ctx* c_, int ph_) : c(c_), ph(ph_) {
-        if (c->prof.on && c->prof.count[ph] < Prof::CAP)
+        if (c->prof.on && (c->prof.mask >> ph & 1) && c->prof.count[ph] < Prof::CAP)
             (void)hipEventRecord(c->prof.ev[ph][0][c->prof.count[ph]], c->stream);
     }
     ~PhaseTimer() {
-        if (c->prof.on && c->prof.count[ph] < Prof::CAP) {
+        if (c->prof.on && (c->prof.mask >> ph & 1) && c->prof.count[ph] < Prof::CAP) {
             (void)hipEventRecord(c->prof.ev[ph][1][c->prof.count[ph]], c->stream);
             ++c->prof.count[ph];
         }
@@ -821,6 +822,7 @@ extern "C" int cakf_step(cakf_ctx* c, const int32_t* idx, const float* y, int m,
 
 extern "C" int cakf_profile_enable(cakf_ctx* c, int on) {
     if (!c) return CAKF_E_ARG;
+    c->prof.mask = on & ((1 << CAKF_PHASES) - 1);
     if (!on) {
         prof_free(c);
         return CAKF_OK;

@@ -161,8 +161,17 @@ class CAKF:
         (a sequence of cakf_tape_step; see paper_2405_08971_amd.autograd)."""
         return L.cakf_loglik_grad(self.ctx, tape)
 
-    def profile(self, on: bool = True):
-        L.cakf_profile_enable(self.ctx, on)
+    def profile(self, on=True):
+        """on: True (all phases), False (off), or an iterable of phase names."""
+        if on is True:
+            mask = -1
+        elif not on:
+            mask = 0
+        else:
+            mask = 0
+            for name in on:
+                mask |= 1 << L.PHASES.index(name)
+        L.cakf_profile_enable(self.ctx, mask)
 
     def profile_read(self):
         return L.cakf_profile_read(self.ctx)
