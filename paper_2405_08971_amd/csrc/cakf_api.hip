@@ -82,6 +82,10 @@ struct cakf_ctx {
     double* offdiag;
     int* info;
     float* Vr;
+    // tridiagonalisation (K <= TD_MAXK): reflectors, tau, exchange vectors, barrier words
+    double *tdV, *tdtau, *tdp, *tdrow;
+    unsigned* tdctr;
+    int* tdabort;
     void* blas_ws;
     Prof prof;
     // smoother (allocated when cfg.smoother != 0)
@@ -150,7 +154,8 @@ static void free_all(cakf_ctx* c) {
                     c->part, c->cpart, c->colvec, c->fupart, c->ttpart, c->mpart, c->Linv,
                     c->LinvT, c->L, c->LSinv, c->LSinvT,
                     c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->Bth, c->Btl, c->G, c->gwork, c->eigval,
-                    c->offdiag, c->info, c->Vr, c->blas_ws, c->Xp, c->sm_ws, c->sm_W[0],
+                    c->offdiag, c->info, c->Vr, c->tdV, c->tdtau, c->tdp, c->tdrow, c->tdctr,
+                    c->tdabort, c->blas_ws, c->Xp, c->sm_ws, c->sm_W[0],
                     c->sm_W[1], c->sm_B, c->sm_Y, c->sm_Z, c->sm_Q, c->sm_Gr, c->sm_R,
                     c->sm_WR, c->sm_Bth, c->sm_Btl, c->gMb[0], c->gMb[1], c->gmb, c->gYb,
                     c->gBq, c->gBb, c->gbpart, c->gspart, c->gQb, c->gMob, c->gZr, c->gCc,
@@ -257,6 +262,14 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     rc |= dalloc(&c->offdiag, c->Kmax);
     rc |= dalloc(&c->info, 1);
     rc |= dalloc(&c->Vr, (size_t)c->Kmax * c->r);
+    if (c->Kmax >= 3 && c->Kmax <= TD_MAXK) {
+        rc |= dalloc(&c->tdV, (size_t)c->Kmax * c->Kmax);
+        rc |= dalloc(&c->tdtau, c->Kmax);
+        rc |= dalloc(&c->tdp, 2 * (size_t)c->Kmax);
+        rc |= dalloc(&c->tdrow, 2 * (size_t)c->Kmax);
+        rc |= dalloc(&c->tdctr, 1);
+        rc |= dalloc(&c->tdabort, 1);
+    }
     if (cfg->smoother) {
         c->np = round_up(c->n, SYM_TILE);
         c->bps = round_up(1 + c->r, 32);
@@ -320,6 +333,10 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     rocblas_start_device_memory_size_query(c->blas);
     rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, c->Kmax, c->G,
                      c->Kmax, c->eigval, c->offdiag, c->info);
+    rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, c->Kmax, c->eigval, c->offdiag, c->G,
+                     c->Kmax, c->info);
+    rocsolver_dormtr(c->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                     c->Kmax, c->r, c->G, c->Kmax, c->eigval, c->G, c->Kmax);
     rocblas_stop_device_memory_size_query(c->blas, &ws);
     ws = std::max<size_t>(ws, 1 << 20);
     if (hipMalloc(&c->blas_ws, ws) != hipSuccess ||
@@ -406,6 +423,11 @@ extern "C" int cakf_predict(cakf_ctx* c) {
 __global__ void k_empty_record(double* loglik, int* n_actions) {
     if (loglik) *loglik = 0.0;
     if (n_actions) *n_actions = 0;
+}
+
+// A bounded wait of the tridiagonalisation that gave up counts as a non-finite event.
+__global__ void k_note_abort(const int* abort_flag, Diag* dg) {
+    if (*abort_flag) dg->nonfinite += 1;
 }
 
 __global__ void k_count_diag(const LoopState* ls, Diag* dg) {
@@ -536,8 +558,27 @@ static int truncate_factor(cakf_ctx* c, const float* M, int ld, int K, int r, fl
     }
     {
         PhaseTimer t(c, CAKF_PHASE_EIG);
-        BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K, c->G,
-                                  K, c->eigval, c->offdiag, c->info));
+        // G = Q T Q^T in one cooperative launch, T's eigenvectors by divide and conquer,
+        // then only the r leading ones back-transformed.  Larger K (or a device that cannot
+        // co-schedule the launch) takes the library's dense solver.
+        bool done = false;
+        if (c->tdV && K >= 3 && K <= TD_MAXK) {
+            if (launch_tridiag(c->G, K, c->tdV, c->tdtau, c->eigval, c->offdiag, c->tdp,
+                               c->tdrow, c->tdctr, c->tdabort, st) == hipSuccess) {
+                hipLaunchKernelGGL(k_note_abort, dim3(1), dim3(1), 0, st, c->tdabort, c->diag);
+                BLAS_TRY(rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, K, c->eigval,
+                                          c->offdiag, c->G, K, c->info));
+                BLAS_TRY(rocsolver_dormtr(c->blas, rocblas_side_left, rocblas_fill_lower,
+                                          rocblas_operation_none, K, r, c->tdV, K, c->tdtau,
+                                          c->G + (size_t)(K - r) * K, K));
+                done = true;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (!done)
+            BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K,
+                                      c->G, K, c->eigval, c->offdiag, c->info));
     }
     {
         PhaseTimer t(c, CAKF_PHASE_ROTATE);

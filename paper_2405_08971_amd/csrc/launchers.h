@@ -108,6 +108,14 @@ void launch_smooth_messages(const float* Bs, int ldb, int n, const int32_t* idx,
                             hipStream_t st);
 void launch_pad_points(const float4* Xs, int n, int np, float4* Xp, hipStream_t st);
 
+// ---- eig.hip
+constexpr int TD_MAXK = 640;        // largest K of the one-launch tridiagonalisation
+int tridiag_max_k();
+int tridiag_workgroups(int K);
+hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double* d, double* e,
+                          double* pbuf, double* rowbuf, unsigned* ctr, int* abort_flag,
+                          hipStream_t st);
+
 // ---- adjoint.hip
 // launch shape of k_adj_tiles: gx blocks of 32 q-points x gy slices of rps p-points
 void adj_tiles_geometry(int np_, int mq, int* gx, int* gy, int* rps);
