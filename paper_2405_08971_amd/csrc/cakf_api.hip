@@ -556,33 +556,31 @@ static int truncate_factor(cakf_ctx* c, const float* M, int ld, int K, int r, fl
         PhaseTimer t(c, CAKF_PHASE_GRAM);
         launch_gram64(M, c->n, ld, K, c->G, c->gwork, c->gram_work_elems, st);
     }
+    bool picked = false;
     {
         PhaseTimer t(c, CAKF_PHASE_EIG);
         // G = Q T Q^T in one cooperative launch, T's eigenvectors by divide and conquer,
-        // then only the r leading ones back-transformed.  Larger K (or a device that cannot
-        // co-schedule the launch) takes the library's dense solver.
-        bool done = false;
+        // then only the r leading ones back-transformed (into V_r directly).  Larger K, or
+        // a device that cannot co-schedule the launch, takes the library's dense solver.
         if (c->tdV && K >= 3 && K <= TD_MAXK) {
             if (launch_tridiag(c->G, K, c->tdV, c->tdtau, c->eigval, c->offdiag, c->tdp,
                                c->tdrow, c->tdctr, c->tdabort, st) == hipSuccess) {
                 hipLaunchKernelGGL(k_note_abort, dim3(1), dim3(1), 0, st, c->tdabort, c->diag);
                 BLAS_TRY(rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, K, c->eigval,
                                           c->offdiag, c->G, K, c->info));
-                BLAS_TRY(rocsolver_dormtr(c->blas, rocblas_side_left, rocblas_fill_lower,
-                                          rocblas_operation_none, K, r, c->tdV, K, c->tdtau,
-                                          c->G + (size_t)(K - r) * K, K));
-                done = true;
+                launch_backtransform(c->G, c->tdV, c->tdtau, K, r, c->Vr, rotation, st);
+                picked = true;
             } else {
                 (void)hipGetLastError();
             }
         }
-        if (!done)
+        if (!picked)
             BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K,
                                       c->G, K, c->eigval, c->offdiag, c->info));
     }
     {
         PhaseTimer t(c, CAKF_PHASE_ROTATE);
-        launch_pick_rotation(c->G, K, r, c->Vr, rotation, st);
+        if (!picked) launch_pick_rotation(c->G, K, r, c->Vr, rotation, st);
         const float one = 1.0f, zero = 0.0f;
         // Mout (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n)
         BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, r,

@@ -1,8 +1,9 @@
 // Householder tridiagonalisation of the truncation's FP64 Gram matrix on gfx950 (one
 // cooperative launch), the first stage of the symmetric eigensolver behind Truncate
 // (Sec. 3.2): G = Q T Q^T with T tridiagonal, Q = H_0 H_1 ... H_{K-3},
-// H_j = I - tau_j v_j v_j^T.  The tridiagonal eigenproblem (divide and conquer) and the
-// back-transformation Q Z are rocSOLVER calls made by the host.
+// H_j = I - tau_j v_j v_j^T, and the back-transformation Q Z of the leading
+// eigenvectors of T.  The tridiagonal eigenproblem itself (divide and conquer) is a
+// rocSOLVER call made by the host.
 //
 // Why one launch: the reduction is a chain of K - 2 dependent steps, each a symmetric
 // matrix-vector product with the trailing matrix and a rank-2 update.  As separate
@@ -18,8 +19,7 @@
 //   applies update j and forms its rows of p_{j+1}; the owner of row j+2 publishes it.
 // Vectors are double-buffered by the parity of j, so a workgroup one step ahead never
 // overwrites what a slower one still reads.  The reflector of step j follows LAPACK's
-// convention (dlarfg: v_j[j+1] = 1, beta = -sign(alpha) ||x||), so the output is
-// exactly what the library back-transformation expects.
+// convention (dlarfg: v_j[j+1] = 1, beta = -sign(alpha) ||x||).
 //
 // The barrier is a monotonically increasing counter (one device-scope atomic add per
 // workgroup and step).  Co-residency of all workgroups is guaranteed by the cooperative
@@ -209,6 +209,96 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
                     (void*)&pbuf, (void*)&rowbuf, (void*)&ctr, (void*)&abort_flag};
     return hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(nwg), dim3(TD_THREADS), args,
                                       0, st);
+}
+
+// ------------------------------------------------------------------ back-transformation
+// V_r = Q Z_r for the r leading eigenvectors of T: Z holds T's eigenvectors as columns
+// (column-major, ascending eigenvalues), so output column c (descending order) starts as
+// Z's column K - 1 - c; the reflectors are applied last-to-first, z <- z - tau_j v_j
+// (v_j^T z).  Each wave keeps two columns in registers (lane l holds rows l + 64 u); a
+// workgroup stages BT_CHUNK reflectors at a time in LDS for its four waves.  Writes
+// Vr (FP32, column-major K x r) and, if asked, rot (FP64, row-major K x r).
+constexpr int BT_CHUNK = 8;
+
+template <int U>
+__global__ __launch_bounds__(256) void k_backtransform(const double* __restrict__ Z,
+                                                       const double* __restrict__ Vh,
+                                                       const double* __restrict__ tau, int K,
+                                                       int r, float* __restrict__ Vr,
+                                                       double* __restrict__ rot) {
+    __shared__ double vs[BT_CHUNK][64 * U];
+    __shared__ double ts[BT_CHUNK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col0 = (blockIdx.x * 4 + wave) * 2;
+    double z[2][U];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = col0 + q;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = lane + 64 * u;
+            z[q][u] = (c < r && k < K) ? Z[(size_t)(K - 1 - c) * K + k] : 0.0;
+        }
+    }
+    for (int j0 = K - 3; j0 >= 0; j0 -= BT_CHUNK) {
+        __syncthreads();
+        for (int e = tid; e < BT_CHUNK * 64 * U; e += 256) {
+            const int jj = e / (64 * U), k = e % (64 * U);
+            const int j = j0 - jj;
+            double v = 0.0;
+            if (j >= 0 && k < K && k >= j + 1) v = (k == j + 1) ? 1.0 : Vh[(size_t)j * K + k];
+            vs[jj][k] = v;
+        }
+        if (tid < BT_CHUNK) ts[tid] = (j0 - tid >= 0) ? tau[j0 - tid] : 0.0;
+        __syncthreads();
+        const int njj = min(BT_CHUNK, j0 + 1);
+        for (int jj = 0; jj < njj; ++jj) {
+            const double t = ts[jj];
+            double vl[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) vl[u] = vs[jj][lane + 64 * u];
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                d0 = __builtin_fma(vl[u], z[0][u], d0);
+                d1 = __builtin_fma(vl[u], z[1][u], d1);
+            }
+            const double f0 = t * wave_sum(d0), f1 = t * wave_sum(d1);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                z[0][u] = __builtin_fma(-f0, vl[u], z[0][u]);
+                z[1][u] = __builtin_fma(-f1, vl[u], z[1][u]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = col0 + q;
+        if (c >= r) continue;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = lane + 64 * u;
+            if (k < K) {
+                Vr[(size_t)c * K + k] = (float)z[q][u];
+                if (rot) rot[(size_t)k * r + c] = z[q][u];
+            }
+        }
+    }
+}
+
+void launch_backtransform(const double* Z, const double* Vh, const double* tau, int K, int r,
+                          float* Vr, double* rot, hipStream_t st) {
+    const int blocks = (r + 7) / 8;
+    const int u = (K + 63) / 64;
+#define CAKF_BT(N)                                                                          \
+    hipLaunchKernelGGL(k_backtransform<N>, dim3(blocks), dim3(256), 0, st, Z, Vh, tau, K, r, \
+                       Vr, rot)
+    if (u <= 2) CAKF_BT(2);
+    else if (u <= 4) CAKF_BT(4);
+    else if (u <= 6) CAKF_BT(6);
+    else if (u <= 8) CAKF_BT(8);
+    else CAKF_BT(10);
+#undef CAKF_BT
 }
 
 }  // namespace cakf

@@ -115,6 +115,8 @@ int tridiag_workgroups(int K);
 hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double* d, double* e,
                           double* pbuf, double* rowbuf, unsigned* ctr, int* abort_flag,
                           hipStream_t st);
+void launch_backtransform(const double* Z, const double* Vh, const double* tau, int K, int r,
+                          float* Vr, double* rot, hipStream_t st);
 
 // ---- adjoint.hip
 // launch shape of k_adj_tiles: gx blocks of 32 q-points x gy slices of rps p-points
