@@ -33,7 +33,7 @@
 
 namespace cakf {
 
-constexpr int TD_THREADS = 256;
+constexpr int TD_THREADS = 512;
 constexpr int TD_LDS = 12800;           // doubles of matrix rows per workgroup (100 KiB)
 
 int tridiag_max_k() { return TD_MAXK; }
@@ -47,7 +47,9 @@ __device__ __forceinline__ double td_block_sum(double v, double* red) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    const double s = (red[0] + red[1]) + (red[2] + red[3]);
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < TD_THREADS / 64; ++w) s += red[w];
     __syncthreads();
     return s;
 }
