@@ -131,15 +131,21 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
                 ah[t] = (__bf16)ka;
                 if constexpr (X3) al[t] = (__bf16)(ka - (float)ah[t]);
             }
+            // the three products of each column tile are issued NT apart, so that no
+            // MFMA waits on the result of the one before it
 #pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                const bf16x8 b = bh[c * 32 + rl][ks * 2 + half];
-                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b, acc[c], 0, 0, 0);
-                if constexpr (X3) {
-                    const bf16x8 b2 = bl[c * 32 + rl][ks * 2 + half];
-                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b2, acc[c], 0, 0, 0);
-                }
+            for (int c = 0; c < NT; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    ah, bh[c * 32 + rl][ks * 2 + half], acc[c], 0, 0, 0);
+            if constexpr (X3) {
+#pragma unroll
+                for (int c = 0; c < NT; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        al, bh[c * 32 + rl][ks * 2 + half], acc[c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < NT; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        ah, bl[c * 32 + rl][ks * 2 + half], acc[c], 0, 0, 0);
             }
         }
     }

@@ -6,31 +6,37 @@
 
 namespace cakf {
 
-constexpr int GT = 32;        // Gram tile side
+constexpr int GT = 64;        // Gram tile side
 constexpr int GROWS = 32;     // factor rows staged per LDS chunk
 
 // Partial Gram tiles: block (tile, split) accumulates M[rows, c-block]^T M[rows, d-block]
-// over its row range in FP64 (FP32 inputs), for lower-triangle tiles c-block >= d-block.
+// over its row range in FP64 (FP32 inputs; each product is exact in FP64), for
+// lower-triangle tiles c-block >= d-block.  Each thread owns a 4 x 4 set of outputs and
+// reads one float4 of each operand per staged row.
 __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ M, int n,
                                                       int ldM, int K, int nsplit,
                                                       double* __restrict__ work) {
-    __shared__ float As[GROWS][GT + 1], Bs[GROWS][GT + 1];
-    const int nt = (K + GT - 1) / GT;
+    __shared__ float As[GROWS][GT + 4], Bs[GROWS][GT + 4];
     const int tile = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
     int tc = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
     while ((tc + 1) * (tc + 2) / 2 <= tile) ++tc;
     while (tc * (tc + 1) / 2 > tile) --tc;
     const int td = tile - tc * (tc + 1) / 2;       // td <= tc
-    (void)nt;
     const int c0 = tc * GT, d0 = td * GT;
     const int rows_per = (n + nsplit - 1) / nsplit;
     const int r0 = split * rows_per, r1 = min(n, r0 + rows_per);
     const int tid = threadIdx.x;
     const int ti = tid >> 4, tj = tid & 15;
-    double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
     for (int p0 = r0; p0 < r1; p0 += GROWS) {
         __syncthreads();
-        for (int e = tid; e < GROWS * GT; e += 256) {
+#pragma unroll
+        for (int u = 0; u < GROWS * GT / 256; ++u) {
+            const int e = tid + 256 * u;
             const int rr = e / GT, cc = e % GT;
             const int p = p0 + rr;
             const bool okr = p < r1;
@@ -38,22 +44,29 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
             Bs[rr][cc] = (okr && d0 + cc < K) ? M[(size_t)p * ldM + d0 + cc] : 0.0f;
         }
         __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
         for (int rr = 0; rr < GROWS; ++rr) {
-            const double a0 = As[rr][2 * ti], a1 = As[rr][2 * ti + 1];
-            const double b0 = Bs[rr][2 * tj], b1 = Bs[rr][2 * tj + 1];
-            acc00 = __builtin_fma(a0, b0, acc00);
-            acc01 = __builtin_fma(a0, b1, acc01);
-            acc10 = __builtin_fma(a1, b0, acc10);
-            acc11 = __builtin_fma(a1, b1, acc11);
+            const float4 a = *reinterpret_cast<const float4*>(&As[rr][4 * ti]);
+            const float4 b = *reinterpret_cast<const float4*>(&Bs[rr][4 * tj]);
+            const double av[4] = {a.x, a.y, a.z, a.w};
+            const double bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_fma(av[x], bv[y], acc[x][y]);
         }
     }
     double* w = work + (size_t)split * K * K;
-    const int c = c0 + 2 * ti, dd = d0 + 2 * tj;
-    if (c < K && dd < K) w[(size_t)c * K + dd] = acc00;
-    if (c < K && dd + 1 < K) w[(size_t)c * K + dd + 1] = acc01;
-    if (c + 1 < K && dd < K) w[(size_t)(c + 1) * K + dd] = acc10;
-    if (c + 1 < K && dd + 1 < K) w[(size_t)(c + 1) * K + dd + 1] = acc11;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const int c = c0 + 4 * ti + x;
+        if (c >= K) continue;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int dd = d0 + 4 * tj + y;
+            if (dd < K) w[(size_t)c * K + dd] = acc[x][y];
+        }
+    }
 }
 
 // G = sum over splits (fixed order), lower tiles mirrored to the full symmetric matrix.
