@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--no-fp32-compare", action="store_true",
                    help="skip the FP32-plain run reported next to the headline mode")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-next-rows", action="store_true",
+                   help="skip the gradient and smoother timings on their own workloads")
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 256 MiB device copy (counter calibration)")
@@ -156,6 +158,83 @@ def copy_probe():
         torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": a.numel() * 4, "launches": 3}), flush=True)
+
+
+def next_rows(seed=0):
+    """The rows built after the hot path, each timed on its own workload (not part of the
+    headline):
+      * the derivative of the log-likelihood (reverse sweep, cakf_loglik_grad) on the
+        n = 16384 differentiation workload (Matern-3/2, m = 4096, i = 64, r = 256, FP32),
+        over T = 50 steps: the forward pass with its tape, then the backward sweep;
+      * the filter and the computation-aware RTS smoother (Alg. 3) on the n = 16384
+        great-circle workload (Matern-3/2, m = 4096, i = 64, r = 256), T = 100."""
+    import torch
+    from paper_2405_08971_amd.autograd import loglik
+    from paper_2405_08971_amd.filter import CAKF, Record
+    from paper_2405_08971_amd.workload import CONFIGS, Workload
+
+    out = {}
+    cfg = CONFIGS["c4"]
+    wl = Workload(cfg, seed=seed)
+    X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
+    steps = device_inputs(wl, range(1, cfg.T + 1))
+    theta = torch.tensor([cfg.ell, cfg.ell_t, cfg.sigma_f2, cfg.noise_var], dtype=torch.float64,
+                         requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ll = loglik(theta, X, steps, nu2=cfg.nu2, dt=cfg.dt, max_obs=cfg.m, max_actions=cfg.i,
+                max_rank=cfg.r, prec="fp32")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ll.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["loglik_grad"] = {
+        "workload": f"{cfg.name}: n={cfg.n} sphere, Matern-{cfg.nu2}/2 chordal, m={cfg.m}, "
+                    f"i={cfg.i} CG actions, r={cfg.r}, T={cfg.T}, fp32",
+        "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+        "backward_ms_per_step": (t2 - t1) * 1e3 / cfg.T,
+        "loglik": float(ll.item()),
+        "grad_ell_ellt_sigmaf2_noise": [float(g) for g in theta.grad.tolist()]}
+    del ll
+    torch.cuda.empty_cache()
+
+    cfg = CONFIGS["c2"]
+    wl = Workload(cfg, seed=seed)
+    X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
+    steps = device_inputs(wl, range(1, cfg.T + 1))
+    f = CAKF(X, nu2=cfg.nu2, dist="geodesic", lengthscale=cfg.ell, signal_var=cfg.sigma_f2,
+             noise_var=cfg.noise_var, ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i,
+             max_rank=cfg.r, policy="cg", prec="fp32", smoother=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd = []
+    for idx, y in steps:
+        f.predict()
+        _, Mp = f.state()
+        rec = Record(cfg.m, cfg.i)
+        f.update(idx, y, None, rec)
+        mean, M = f.state()
+        fwd.append((mean, M, Mp, idx, rec))
+        f.truncate()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    f.smooth_begin(fwd[-1][3], fwd[-1][4])
+    for k in range(cfg.T - 2, -1, -1):
+        mean, M, Mp, idx, rec = fwd[k]
+        f.smooth_step(mean, M, Mp, idx, rec)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f.close()
+    out["smoother"] = {
+        "workload": f"{cfg.name}: n={cfg.n} sphere, Matern-{cfg.nu2}/2 great-circle, m={cfg.m}, "
+                    f"i={cfg.i} CG actions, r={cfg.r}, T={cfg.T}, fp32",
+        "filter_ms_per_step": (t1 - t0) * 1e3 / cfg.T,
+        "smoother_ms_per_step": (t2 - t1) * 1e3 / (cfg.T - 1),
+        "note": "filter steps include copying M_k and M_k^- out for the smoother"}
+    del fwd
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(cfg, wl):
@@ -276,6 +355,8 @@ def main():
                           / np.mean(np.abs(mref[sub]))),
             "var": float(np.mean(np.abs(res["var"][sub] - vref[sub]))
                          / np.mean(np.abs(vref[sub])))}
+    if not args.no_next_rows:
+        line["next_rows"] = next_rows(args.seed)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, wl)
     print(json.dumps(line), flush=True)
