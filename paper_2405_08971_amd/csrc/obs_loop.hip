@@ -179,6 +179,30 @@ __device__ __forceinline__ double column_reduce(const Tin* __restrict__ in, size
     return s;
 }
 
+// The first n_t + n_c blocks of a sym_tiles launch: (n_t) t_j = Mo^T s_j into column j
+// of T (column-major, T[l * ldmo + c]) from next_action's per-block partial sums; (n_c)
+// the column products of s_j into colvec, laid out as
+// [u_l^T s_j (l < j) | s_l^T s_j (l <= j) | r0^T s_j].
+__device__ __forceinline__ void sym_extra_block(const ObsDims& d, int j,
+                                                const float* __restrict__ mpart, int nmpart,
+                                                int n_t, float* __restrict__ T,
+                                                const double* __restrict__ cpart, int ncpart,
+                                                int gs, double* __restrict__ colvec) {
+    __shared__ double cred[CR_GRP][CR_POS + 1];
+    if ((int)blockIdx.x < n_t) {
+        const int pos0 = blockIdx.x * CR_POS;
+        const double v = column_reduce(mpart, (size_t)d.ldmo, nmpart, d.rank, pos0, cred);
+        if ((int)threadIdx.x < CR_POS && pos0 + (int)threadIdx.x < d.rank)
+            T[(size_t)j * d.ldmo + pos0 + threadIdx.x] = (float)v;
+    } else {
+        const int pos0 = (blockIdx.x - n_t) * CR_POS;
+        const int npos = 2 * j + 2;
+        const double v = column_reduce(cpart, (size_t)gs, ncpart, npos, pos0, cred);
+        if ((int)threadIdx.x < CR_POS && pos0 + (int)threadIdx.x < npos)
+            colvec[pos0 + threadIdx.x] = v;
+    }
+}
+
 // u_j = K(Xo, Xo) s_j over the upper triangle of SYM_TILE x SYM_TILE tiles.  Tile (P, Q),
 // P <= Q, adds its row sums K_PQ s_Q to slot Q of block P and (P < Q) its column sums
 // K_PQ^T s_P to slot P of block Q; every (slot, block) pair is written exactly once, so
@@ -201,19 +225,7 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const float4* __restrict__ Xo
     if (ls->stop) return;
     const int n_extra = n_t + n_c;
     if ((int)blockIdx.x < n_extra) {
-        __shared__ double cred[CR_GRP][CR_POS + 1];
-        if ((int)blockIdx.x < n_t) {
-            const int pos0 = blockIdx.x * CR_POS;
-            const double v = column_reduce(mpart, (size_t)d.ldmo, nmpart, d.rank, pos0, cred);
-            if ((int)threadIdx.x < CR_POS && pos0 + (int)threadIdx.x < d.rank)
-                T[(size_t)j * d.ldmo + pos0 + threadIdx.x] = (float)v;
-        } else {
-            const int pos0 = (blockIdx.x - n_t) * CR_POS;
-            const int npos = 2 * j + 2;
-            const double v = column_reduce(cpart, (size_t)gs, ncpart, npos, pos0, cred);
-            if ((int)threadIdx.x < CR_POS && pos0 + (int)threadIdx.x < npos)
-                colvec[pos0 + threadIdx.x] = v;
-        }
+        sym_extra_block(d, j, mpart, nmpart, n_t, T, cpart, ncpart, gs, colvec);
         return;
     }
     const int t = blockIdx.x - n_extra;
