@@ -10,8 +10,10 @@ Follows the paper step by step:
                                    Ghat-orthogonalised search directions.
 * Batch update                   - Alg. 2 (Sec. 3.1): one projection S, pseudo-inverse
                                    and a left square root of the projected Gram matrix.
-* Policies                       - CG/Lanczos residual actions (Sec. 3.3, App. E) and
-                                   given actions (any admissible S, App. E).
+* Policies                       - CG/Lanczos residual actions (Sec. 3.3, App. E),
+                                   block-residual actions (the residual split over fixed
+                                   observation groups, b per round) and given actions
+                                   (any admissible S, App. E).
 * Truncate                       - Sec. 3.2: keep the leading r singular directions of
                                    the downdate factor (Eckart-Young-Mirsky).
 * Downdate form of the covariance - Prop. A.2: P_k = Sigma - M_k M_k^T.
@@ -82,6 +84,34 @@ def cg_policy():
     """CG/Lanczos actions: the current residual is the next action (Sec. 3.3)."""
     def policy(i: int, residual: np.ndarray):
         return residual
+    return policy
+
+
+def observation_groups(m: int, b: int):
+    """The fixed partition of the m observations of a step into b contiguous ranges
+    [floor(g m / b), floor((g + 1) m / b)), g = 0 .. b-1 (used by block_residual_policy)."""
+    return [(g * m // b, (g + 1) * m // b) for g in range(b)]
+
+
+def block_residual_policy(b: int, max_actions: int):
+    """Block-residual actions (an admissible choice of S, App. E; not one of the paper's
+    experiments): actions are taken in rounds of b; at the start of a round the current
+    residual r is split over the fixed observation groups, and the round's actions are
+    r restricted to group 0, 1, ..., b_t - 1, b_t = min(b, actions left).  With b = 1
+    every action is the full residual, i.e. the CG policy."""
+    state = {}
+
+    def policy(i: int, residual: np.ndarray):
+        k = (i - 1) % b
+        if k == 0:
+            bt = min(b, max_actions - (i - 1))
+            state["r"] = np.array(residual, np.float64)
+            state["groups"] = observation_groups(residual.size, bt)
+        r = state["r"]
+        g0, g1 = state["groups"][k]
+        s = np.zeros_like(r)
+        s[g0:g1] = r[g0:g1]
+        return s
     return policy
 
 
@@ -258,7 +288,8 @@ def run_filter(model: Model, steps, max_actions: int, r_cap: int, policy: str = 
                form: str = "iterative", rotations=None, m0=None, M0=None) -> List[StepRecord]:
     """Alg. 1.  steps[k-1] = (idx_k, y_k) or None (no data) for k = 1..T.
 
-    policy "cg": residual actions; policy "given": actions[k-1] is S_k (m_k x i).
+    policy "cg": residual actions; policy ("block", b): block-residual actions in rounds
+    of b; policy "given": actions[k-1] is S_k (m_k x i).
     rotations[k-1], if given, replays the truncation rotation of step k."""
     n = model.n
     m = np.zeros(n) if m0 is None else np.asarray(m0, np.float64)
@@ -276,6 +307,8 @@ def run_filter(model: Model, steps, max_actions: int, r_cap: int, policy: str = 
             idx = np.asarray(idx)
             if policy == "cg":
                 pol = cg_policy()
+            elif isinstance(policy, tuple) and policy[0] == "block":
+                pol = block_residual_policy(int(policy[1]), max_actions)
             elif policy == "given":
                 pol = given_policy(np.asarray(actions[k - 1], np.float64))
             else:
