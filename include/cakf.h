@@ -69,9 +69,16 @@ typedef struct cakf_ctx cakf_ctx;
 
 /* Policy (Sec. 3.3): CG - the current residual is the next action (App. E, the
  * policy of all the paper's experiments); GIVEN - the actions are supplied by the
- * caller (any full-rank S is admissible). */
+ * caller (any full-rank S is admissible); BLOCK - block-residual actions, not one of the
+ * paper's experiments but admissible in the same sense: actions come in rounds of
+ * block_actions, each round splitting the residual at its start over fixed contiguous
+ * groups of the observations (group g of b = [floor(g m / b), floor((g + 1) m / b))),
+ * so that one kernel-matrix product with b vectors serves the whole round.  The last
+ * round takes the actions left (b_t = min(b, actions left)); resid_tol must be 0 with
+ * BLOCK (cakf_create returns CAKF_E_ARG otherwise). */
 #define CAKF_POLICY_CG    0
 #define CAKF_POLICY_GIVEN 1
+#define CAKF_POLICY_BLOCK 2
 
 typedef struct {
     int n;                  /* spatial points = state dimension, >= 1                */
@@ -87,6 +94,8 @@ typedef struct {
     int max_actions;        /* action budget i per update, 1..256 (at most m used)   */
     int max_rank;           /* rank cap r of the truncated factor, 1..1024           */
     int policy;             /* CAKF_POLICY_*                                         */
+    int block_actions;      /* actions per round of POLICY_BLOCK, 1..max_actions
+                               (ignored by the other policies)                       */
     double resid_tol;       /* stop when ||r|| <= resid_tol * ||r0||; 0 = never     */
     double pivot_tol;       /* drop action j when its Ghat-orthogonal part keeps no
                                more than pivot_tol of s_j^T Ghat s_j (breakdown);

@@ -180,13 +180,13 @@ static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const 
 
 // Split B (FP32, row-major mp x ldb, columns 0..bp) into transposed BF16 parts:
 // Bth[c * mp + q] = bf16(B[q, c]), Btl = bf16(B - Bth).
-__global__ void k_split_bt(const float* __restrict__ B, int mp, int ldb, int bp,
+__global__ void k_split_bt(const float* __restrict__ B, int mp, int ldb, int bcols, int bp,
                            __bf16* __restrict__ Bth, __bf16* __restrict__ Btl) {
     const size_t total = (size_t)mp * bp;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(e / mp), q = (int)(e % mp);
-        const float v = B[(size_t)q * ldb + c];
+        const float v = c < bcols ? B[(size_t)q * ldb + c] : 0.0f;
         const __bf16 h = (__bf16)v;
         Bth[e] = h;
         Btl[e] = (__bf16)(v - (float)h);
@@ -210,7 +210,7 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
     const int ntiles = (bcols + 31) / 32;
     const size_t total = (size_t)mp * ntiles * 32;
     hipLaunchKernelGGL(k_split_bt, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
-                       dim3(256), 0, st, B, mp, ldb, ntiles * 32, Bth, Btl);
+                       dim3(256), 0, st, B, mp, ldb, bcols, ntiles * 32, Bth, Btl);
     for (int t0 = 0; t0 < ntiles; t0 += 5) {
         const int nt = std::min(5, ntiles - t0);
         if (prec == 2) {

@@ -108,6 +108,11 @@ struct cakf_ctx {
     int gspart_blocks;
     float *gQb, *gMob, *gZr, *gCc;
     double *gW64, *gSr64, *gBb64, *gG1, *gG2, *gX1, *gX2, *gpart, *gacc;
+    // block-residual policy (allocated when cfg.policy == CAKF_POLICY_BLOCK)
+    int bmax, ldz;
+    double* bS64;   // FP64 copy of the actions (mpmax x imax)
+    double* bZ64;   // [Ghat S_round | S_round | r0] in FP64 (mpmax x ldz)
+    double* bG;     // S^T [Ghat S_round | S_round | r0] (imax x ldz)
 };
 
 namespace {
@@ -160,7 +165,7 @@ static void free_all(cakf_ctx* c) {
                     c->sm_WR, c->sm_Bth, c->sm_Btl, c->gMb[0], c->gMb[1], c->gmb, c->gYb,
                     c->gBq, c->gBb, c->gbpart, c->gspart, c->gQb, c->gMob, c->gZr, c->gCc,
                     c->gW64, c->gSr64, c->gBb64, c->gG1, c->gG2, c->gX1, c->gX2, c->gpart,
-                    c->gacc};
+                    c->gacc, c->bS64, c->bZ64, c->bG};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -187,7 +192,12 @@ static int validate(const cakf_config* c) {
     if (!(c->ou_coeff > 0) || c->ou_coeff > 1) return CAKF_E_ARG;
     if (c->max_obs < 1 || c->max_actions < 1 || c->max_actions > 256) return CAKF_E_ARG;
     if (c->max_rank < 1 || c->max_rank > 1024) return CAKF_E_ARG;
-    if (c->policy != CAKF_POLICY_CG && c->policy != CAKF_POLICY_GIVEN) return CAKF_E_ARG;
+    if (c->policy != CAKF_POLICY_CG && c->policy != CAKF_POLICY_GIVEN &&
+        c->policy != CAKF_POLICY_BLOCK)
+        return CAKF_E_ARG;
+    if (c->policy == CAKF_POLICY_BLOCK &&
+        (c->block_actions < 1 || c->block_actions > c->max_actions || c->resid_tol != 0))
+        return CAKF_E_ARG;
     if (c->prec != CAKF_PREC_FP32 && c->prec != CAKF_PREC_BF16 && c->prec != CAKF_PREC_BF16X3)
         return CAKF_E_ARG;
     if (c->resid_tol < 0 || c->pivot_tol < 0) return CAKF_E_ARG;
@@ -315,6 +325,13 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         rc |= dalloc(&c->gpart, (n + 3) / 4);
         rc |= dalloc(&c->gacc, 4);
     }
+    if (cfg->policy == CAKF_POLICY_BLOCK) {
+        c->bmax = cfg->block_actions;
+        c->ldz = 2 * c->bmax + 1;
+        rc |= dalloc(&c->bS64, (size_t)c->mpmax * c->imax);
+        rc |= dalloc(&c->bZ64, (size_t)c->mpmax * c->ldz);
+        rc |= dalloc(&c->bG, (size_t)c->imax * c->ldz);
+    }
     if (rc) {
         free_all(c);
         delete c;
@@ -438,6 +455,66 @@ __global__ void k_count_diag(const LoopState* ls, Diag* dg) {
     dg->loglik += ls->loglik;
 }
 
+// Row-major GEMM C (M x N) = alpha op(A) op(B) + beta C through column-major rocBLAS
+// (a row-major matrix is its transpose in column-major storage).
+static rocblas_status sgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K,
+                               float alpha, const float* A, int lda, const float* B, int ldb,
+                               float beta, float* C, int ldc) {
+    return rocblas_sgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
+                         &alpha, B, ldb, A, lda, &beta, C, ldc);
+}
+
+static rocblas_status dgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K,
+                               double alpha, const double* A, int lda, const double* B,
+                               int ldb, double beta, double* C, int ldc) {
+    return rocblas_dgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
+                         &alpha, B, ldb, A, lda, &beta, C, ldc);
+}
+
+// The action loop of the block-residual policy: rounds of bt actions.  A round splits the
+// current residual over bt observation groups (the new action columns), multiplies them by
+// the prior covariance of the observed points in one block product, subtracts the low-rank
+// part with two GEMMs, and forms all Gram columns of the round with one FP64 GEMM,
+//     G = S^T [Ghat S_round | S_round | r0]   (rows: every action so far),
+// from which the incremental Cholesky step takes one column per action.
+static int block_rounds(cakf_ctx* c, const ObsDims& d, int imax, hipStream_t st) {
+    const int nu2 = c->cfg.kernel, dist = c->cfg.dist, m = d.m;
+    const float noise = (float)c->cfg.noise_var;
+    for (int j0 = 0; j0 < imax;) {
+        const int bt = std::min(c->bmax, imax - j0);
+        launch_block_residual(c->U, c->V, c->S, c->r0, c->beta, noise, d, j0, bt, c->ls, st);
+        launch_block_product(nu2, dist, c->cfg.prec, c->Xo, m, c->Xo, m, d.mp, c->S + j0,
+                             d.imax, bt, c->Bth, c->Btl, (float)c->cfg.signal_var, c->U + j0,
+                             d.imax, st);
+        if (d.rank > 0) {
+            const float one = 1.0f, zero = 0.0f;
+            // T[:, j0 + g] = Mo^T s_(j0 + g)   (column-major, ld ldmo)
+            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
+                                   d.rank, bt, m, &one, c->Mo, c->ldmo, c->S + j0, d.imax,
+                                   &zero, c->T + (size_t)j0 * c->ldmo, c->ldmo));
+            // V[:, j0 + g] = Mo T[:, j0 + g]   (row-major rows of V, ld imax)
+            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                   bt, m, d.rank, &one, c->T + (size_t)j0 * c->ldmo, c->ldmo,
+                                   c->Mo, c->ldmo, &zero, c->V + j0, d.imax));
+        }
+        launch_block_pack64(c->U, c->V, c->S, c->r0, noise, d, j0, bt, d.rank > 0 ? 1 : 0,
+                            c->bS64, c->bZ64, c->ldz, st);
+        BLAS_TRY(dgemm_rm(c->blas, true, false, j0 + bt, 2 * bt + 1, m, 1.0, c->bS64, d.imax,
+                          c->bZ64, c->ldz, 0.0, c->bG, c->ldz));
+        for (int g = 0; g < bt; ++g) {
+            PhaseTimer t(c, CAKF_PHASE_TAIL);
+            launch_tail(nullptr, nullptr, 0, nullptr, d, j0 + g, c->cfg.noise_var,
+                        c->cfg.resid_tol, c->cfg.pivot_tol, c->Linv, c->LinvT, c->L, c->LSinv,
+                        c->LSinvT, c->alpha, c->beta, c->ls, st, c->bG, c->ldz, g, bt + g,
+                        2 * bt);
+        }
+        j0 += bt;
+    }
+    return CAKF_OK;
+}
+
 extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int m,
                            const float* actions, const cakf_record* rec) {
     if (!c || m < 0 || m > c->mmax) return CAKF_E_ARG;
@@ -450,7 +527,8 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     }
     if (!idx || !y) return CAKF_E_ARG;
     const bool cg = c->cfg.policy == CAKF_POLICY_CG;
-    if (!cg && !actions) return CAKF_E_ARG;
+    const bool block = c->cfg.policy == CAKF_POLICY_BLOCK;
+    if (c->cfg.policy == CAKF_POLICY_GIVEN && !actions) return CAKF_E_ARG;
     if (c->rank > c->r) return CAKF_E_STATE;
     const int imax = std::min(c->imax, m);
     ObsDims d;
@@ -469,9 +547,12 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     HIP_TRY(hipMemsetAsync(c->LSinvT, 0, tri, st));
     HIP_TRY(hipMemsetAsync(c->alpha, 0, c->imax * sizeof(double), st));
     HIP_TRY(hipMemsetAsync(c->beta, 0, c->imax * sizeof(double), st));
-    launch_gather(c->Xs, c->n, c->mean, M, c->ldM, idx, y, actions, cg ? 1 : 0, d, c->Xo, c->r0,
-                  c->Mo, c->S, c->U, c->ls, st);
-    if (d.rank > 0) {
+    launch_gather(c->Xs, c->n, c->mean, M, c->ldM, idx, y, block ? nullptr : actions,
+                  (cg || block) ? 1 : 0, d, c->Xo, c->r0, c->Mo, c->S, c->U, c->ls, st);
+    if (block) {
+        const int rc = block_rounds(c, d, imax, st);
+        if (rc) return rc;
+    } else if (d.rank > 0) {
         if (cg) {
             int nb = 0;
             launch_colsum_partial(c->Mo, c->ldmo, m, d.rank, c->r0, 1, c->mpart, c->ldmo, st, &nb);
@@ -488,9 +569,10 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     const float noise = (float)c->cfg.noise_var;
     // column products of s_0
     int ncp = 0, nmpart = 0;
-    launch_next_action(0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise, d, 0, c->mpart,
-                       c->cpart, c->gs, c->ls, st, &ncp);
-    for (int j = 0; j < imax; ++j) {
+    if (!block)
+        launch_next_action(0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise, d, 0,
+                           c->mpart, c->cpart, c->gs, c->ls, st, &ncp);
+    for (int j = 0; j < (block ? 0 : imax); ++j) {
         {
             PhaseTimer t(c, CAKF_PHASE_SYM_TILES);
             launch_sym_tiles(nu2, dist, c->Xo, c->S, d, j, c->part,
@@ -603,24 +685,6 @@ extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
 
 
 // ------------------------------------------------------- log-likelihood derivative
-// Row-major GEMM C (M x N) = alpha op(A) op(B) + beta C through column-major rocBLAS
-// (a row-major matrix is its transpose in column-major storage).
-static rocblas_status sgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K,
-                               float alpha, const float* A, int lda, const float* B, int ldb,
-                               float beta, float* C, int ldc) {
-    return rocblas_sgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
-                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
-                         &alpha, B, ldb, A, lda, &beta, C, ldc);
-}
-
-static rocblas_status dgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K,
-                               double alpha, const double* A, int lda, const double* B,
-                               int ldb, double beta, double* C, int ldc) {
-    return rocblas_dgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
-                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
-                         &alpha, B, ldb, A, lda, &beta, C, ldc);
-}
-
 extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, double* grad) {
     if (!c || !grad || T < 1 || !tape || !c->gMb[0]) return CAKF_E_ARG;
     hipStream_t st = c->stream;

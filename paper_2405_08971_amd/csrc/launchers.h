@@ -70,7 +70,14 @@ void launch_form_u(const float* part, const float* S, float* U, const float* T,
 void launch_tail(const double* colvec, const double* fupart, int nfu, const double* ttv,
                  const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
                  double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
-                 double* alpha, double* beta, LoopState* ls, hipStream_t st);
+                 double* alpha, double* beta, LoopState* ls, hipStream_t st,
+                 const double* gdir = nullptr, int ldg = 0, int jc = 0, int jq = 0, int jr = 0);
+void launch_block_residual(const float* U, const float* V, float* S, const float* r0,
+                           const double* beta, float noise_var, const ObsDims& d, int j0, int bt,
+                           const LoopState* ls, hipStream_t st);
+void launch_block_pack64(const float* U, const float* V, const float* S, const float* r0,
+                         float noise_var, const ObsDims& d, int j0, int bt, int lowrank,
+                         double* S64, double* Z64, int ldz, hipStream_t st);
 void launch_next_action(int resid, const float* U, const float* Mo, const float* r0, float* S,
                         float* V, const double* beta, const float* T, float noise_var,
                         const ObsDims& d, int jt, float* mpart, double* cpart, int gs,

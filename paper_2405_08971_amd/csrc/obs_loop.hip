@@ -468,7 +468,9 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
                                                        double* __restrict__ LSinvT,
                                                        double* __restrict__ alpha,
                                                        double* __restrict__ beta,
-                                                       LoopState* __restrict__ ls) {
+                                                       LoopState* __restrict__ ls,
+                                                       const double* __restrict__ gdir,
+                                                       int ldg, int jc, int jq, int jr) {
     __shared__ double Ccol[256], Qcol[256], lrow[256], lsrow[256], nrow[256], alph[256];
     __shared__ double red[3][TAIL_THREADS / 64];
     const int tid = threadIdx.x;
@@ -477,21 +479,29 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
     const int J = j + 1;
     // 1. column j: u_l^T s_j (l < j) and s_l^T s_j (l <= j) from the column products,
     //    s_j^T u_j from form_u's partial sums
+    //    (direct mode, gdir != null: the column of C itself, s_l^T Ghat s_j, together
+    //    with s_l^T s_j and r0^T s_j, from columns jc, jq, jr of gdir)
     double fu = 0.0, cj = 0.0, unused = 0.0;
-    for (int b = tid; b < nfu; b += TAIL_THREADS) fu += fupart[b];
-    if (tid == 0) cj = colvec[2 * j + 1];
+    if (!gdir)
+        for (int b = tid; b < nfu; b += TAIL_THREADS) fu += fupart[b];
+    if (tid == 0) cj = gdir ? gdir[(size_t)j * ldg + jr] : colvec[2 * j + 1];
     double gcol = 0.0, qcol = 0.0, tt = 0.0, al = 0.0;
     if (tid < J) {
-        gcol = tid < j ? colvec[tid] : 0.0;
-        qcol = colvec[j + tid];
-        tt = d.rank > 0 ? ttv[tid] : 0.0;
+        if (gdir) {
+            gcol = gdir[(size_t)tid * ldg + jc];
+            qcol = gdir[(size_t)tid * ldg + jq];
+        } else {
+            gcol = tid < j ? colvec[tid] : 0.0;
+            qcol = colvec[j + tid];
+            tt = d.rank > 0 ? ttv[tid] : 0.0;
+        }
         al = tid < j ? alpha[tid] : 0.0;
     }
     block_sum3(fu, cj, unused, red);
     const double c_j = cj;
     if (tid < J) {
-        const double g = tid < j ? gcol : fu;
-        Ccol[tid] = g - tt + noise_var * qcol;
+        const double g = (gdir || tid < j) ? gcol : fu;
+        Ccol[tid] = gdir ? g : g - tt + noise_var * qcol;
         Qcol[tid] = qcol;
         alph[tid] = al;
     }
@@ -616,10 +626,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
 void launch_tail(const double* colvec, const double* fupart, int nfu, const double* ttv,
                  const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
                  double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
-                 double* alpha, double* beta, LoopState* ls, hipStream_t st) {
+                 double* alpha, double* beta, LoopState* ls, hipStream_t st,
+                 const double* gdir, int ldg, int jc, int jq, int jr) {
     hipLaunchKernelGGL(k_tail, dim3(1), dim3(TAIL_THREADS), 0, st, colvec, fupart, nfu, ttv, d,
                        j, noise_var, resid_tol, pivot_tol, Linv, LinvT, L, LSinv, LSinvT, alpha,
-                       beta, ls);
+                       beta, ls, gdir, ldg, jc, jq, jr);
 }
 
 // ---------------------------------------------------------------------- next_action
@@ -822,6 +833,79 @@ void launch_next_action(int resid, const float* U, const float* Mo, const float*
     else
         launch_na_l<true, 16>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
                               cpart, gs, ls, st);
+}
+
+// ------------------------------------------------------------------ block-residual policy
+// Start of a round of bt actions at action index j0: the residual
+// rho = r0 - (U - Mo T + noise_var S) beta over the j0 actions taken so far, split over bt
+// contiguous observation groups: S[p, j0 + g] = rho[p] if p lies in
+// [floor(g m / bt), floor((g + 1) m / bt)), else 0.  One wave per observation row.
+__global__ __launch_bounds__(256) void k_block_residual(const float* __restrict__ U,
+                                                        const float* __restrict__ V,
+                                                        float* __restrict__ S,
+                                                        const float* __restrict__ r0,
+                                                        const double* __restrict__ beta,
+                                                        float noise_var, ObsDims d, int j0,
+                                                        int bt, const LoopState* __restrict__ ls) {
+    if (ls->stop) return;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= d.mp) return;
+    float rho = 0.0f;
+    if (p < d.m) {
+        float part = 0.0f;
+        for (int l = lane; l < j0; l += 64) {
+            const size_t o = (size_t)p * d.imax + l;
+            const float lr = d.rank > 0 ? V[o] : 0.0f;
+            part = __builtin_fmaf(lr - __builtin_fmaf(noise_var, S[o], U[o]), (float)beta[l], part);
+        }
+        rho = r0[p] + wave_sum(part);
+    }
+    for (int g = lane; g < bt; g += 64) {
+        const int g0 = (int)((long long)g * d.m / bt), g1 = (int)((long long)(g + 1) * d.m / bt);
+        S[(size_t)p * d.imax + j0 + g] = (p >= g0 && p < g1) ? rho : 0.0f;
+    }
+}
+
+void launch_block_residual(const float* U, const float* V, float* S, const float* r0,
+                           const double* beta, float noise_var, const ObsDims& d, int j0, int bt,
+                           const LoopState* ls, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_residual, dim3((d.mp + 3) / 4), dim3(256), 0, st, U, V, S, r0,
+                       beta, noise_var, d, j0, bt, ls);
+}
+
+// FP64 operands of a round's Gram columns, rows p < m: S64[p, j0 + g] = S[p, j0 + g] and
+// Z64[p, :] = [z_g (bt) | s_g (bt) | r0], z = U - V + noise_var S (= Ghat s), g < bt.
+__global__ void k_block_pack64(const float* __restrict__ U, const float* __restrict__ V,
+                               const float* __restrict__ S, const float* __restrict__ r0,
+                               float noise_var, ObsDims d, int j0, int bt, int lowrank,
+                               double* __restrict__ S64, double* __restrict__ Z64, int ldz) {
+    const size_t total = (size_t)d.m * (2 * bt + 1);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int p = (int)(e / (2 * bt + 1)), c = (int)(e % (2 * bt + 1));
+        double v;
+        if (c < bt) {
+            const size_t o = (size_t)p * d.imax + j0 + c;
+            v = (double)U[o] + (double)noise_var * (double)S[o] - (lowrank ? (double)V[o] : 0.0);
+        } else if (c < 2 * bt) {
+            const size_t o = (size_t)p * d.imax + j0 + (c - bt);
+            v = (double)S[o];
+            S64[(size_t)p * d.imax + j0 + (c - bt)] = v;
+        } else {
+            v = (double)r0[p];
+        }
+        Z64[(size_t)p * ldz + c] = v;
+    }
+}
+
+void launch_block_pack64(const float* U, const float* V, const float* S, const float* r0,
+                         float noise_var, const ObsDims& d, int j0, int bt, int lowrank,
+                         double* S64, double* Z64, int ldz, hipStream_t st) {
+    const size_t total = (size_t)d.m * (2 * bt + 1);
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_block_pack64, dim3(blocks), dim3(256), 0, st, U, V, S, r0, noise_var, d,
+                       j0, bt, lowrank, S64, Z64, ldz);
 }
 
 // ----------------------------------------------------------------------- build_block

@@ -39,7 +39,8 @@ class CAKF:
     def __init__(self, X: torch.Tensor, *, nu2: int = 3, dist: str = "euclid",
                  lengthscale: float, signal_var: float = 1.0, noise_var: float,
                  ou_coeff: float, max_obs: int, max_actions: int, max_rank: int,
-                 policy: str = "cg", resid_tol: float = 0.0, pivot_tol: float = 1e-10,
+                 policy: str = "cg", block_actions: int = 8, resid_tol: float = 0.0,
+                 pivot_tol: float = 1e-10,
                  prec: str = "fp32", smoother: bool = False, gradient: bool = False,
                  stream: Optional[torch.cuda.Stream] = None):
         if X.dtype != torch.float32 or X.dim() != 2:
@@ -53,7 +54,8 @@ class CAKF:
             n=self.n, dim=self.dim, X=L.ptr(X), kernel=L.MATERN[nu2], dist=L.DIST[dist],
             lengthscale=lengthscale, signal_var=signal_var, noise_var=noise_var,
             ou_coeff=ou_coeff, max_obs=max_obs, max_actions=max_actions, max_rank=max_rank,
-            policy=L.POLICY[policy], resid_tol=resid_tol, pivot_tol=pivot_tol,
+            policy=L.POLICY[policy], block_actions=block_actions, resid_tol=resid_tol,
+            pivot_tol=pivot_tol,
             prec=L.PREC[prec], smoother=1 if smoother else 0, gradient=1 if gradient else 0,
             stream=L.stream_handle(stream))
         self._X = X

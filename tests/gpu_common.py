@@ -59,10 +59,13 @@ def gpu_run(cfg: Config, X, steps, actions, policy, prec="fp32", probes=None,
 
     dev = "cuda"
     Xd = torch.from_numpy(X).to(dev)
+    block_actions = 1
+    if isinstance(policy, tuple):          # ("block", b), as the oracle names it
+        policy, block_actions = policy[0], int(policy[1])
     f = CAKF(Xd, nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid",
              lengthscale=cfg.ell, signal_var=cfg.sigma_f2, noise_var=cfg.noise_var,
              ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy=policy,
-             pivot_tol=pivot_tol, resid_tol=resid_tol, prec=prec)
+             block_actions=block_actions, pivot_tol=pivot_tol, resid_tol=resid_tol, prec=prec)
     P = None if probes is None else torch.from_numpy(probes.astype(np.float32)).to(dev)
     out = []
     for k, item in enumerate(steps):
