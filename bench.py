@@ -34,6 +34,9 @@ PEAK_BF16 = 2.5e15                     # dense BF16 MFMA flop / s
 PEAK_HBM = 8.0e12                      # B / s
 
 
+BLOCK_SIZES = (8, 32)      # actions per round of the block-residual policy timings
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -62,15 +65,15 @@ def device_inputs(wl, ks):
     return out
 
 
-def make_filter(cfg, X, prec, policy="cg"):
+def make_filter(cfg, X, prec, policy="cg", block_actions=1):
     from paper_2405_08971_amd.filter import CAKF
     return CAKF(X, nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid",
                 lengthscale=cfg.ell, signal_var=cfg.sigma_f2, noise_var=cfg.noise_var,
                 ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r,
-                policy=policy, prec=prec)
+                policy=policy, block_actions=block_actions, prec=prec)
 
 
-def run(cfg, X, inputs, warmup, steps, prec, breakdown=3):
+def run(cfg, X, inputs, warmup, steps, prec, breakdown=3, policy="cg", block_actions=1):
     """Warm-up steps, then the timed steps, then `breakdown` more steps with every phase
     timed (untimed as a whole).  In the timed steps only the dominant kernel's launches
     are bracketed by HIP events (each bracket costs a few microseconds on the stream).
@@ -79,7 +82,7 @@ def run(cfg, X, inputs, warmup, steps, prec, breakdown=3):
     import torch
     from paper_2405_08971_amd.filter import Record
 
-    f = make_filter(cfg, X, prec)
+    f = make_filter(cfg, X, prec, policy, block_actions)
     nrec = warmup + steps + breakdown
     recs = [Record(cfg.m, cfg.i) for _ in range(nrec)]
     for k in range(warmup):
@@ -357,6 +360,21 @@ def main():
                          / np.mean(np.abs(vref[sub])))}
     if not args.no_next_rows:
         line["next_rows"] = next_rows(args.seed)
+        # the block-residual policy on the same workload and inputs (same action budget)
+        blk = {}
+        for b in BLOCK_SIZES:
+            r = run(cfg, X, inputs, args.warmup, args.steps, args.prec, breakdown=0,
+                    policy="block", block_actions=b)
+            blk[f"b={b}"] = {"value": args.steps / r["elapsed"],
+                             "ms_per_step": r["elapsed"] / args.steps * 1e3,
+                             "loglik_per_step": float(np.mean(
+                                 [rec.loglik.item() for rec in r["recs"][args.warmup:]])),
+                             "dropped_actions": r["dropped"]}
+        blk["cg_loglik_per_step"] = float(np.mean(
+            [rec.loglik.item() for rec in res["recs"][args.warmup:]]))
+        blk["workload"] = line["config"]["workload"].replace("CG actions",
+                                                             "block-residual actions")
+        line["next_rows"]["block_policy"] = blk
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, wl)
     print(json.dumps(line), flush=True)

@@ -20,7 +20,8 @@ __global__ __launch_bounds__(256) void k_block_fp32(const float4* __restrict__ X
                                                     const float4* __restrict__ Xo, int m,
                                                     const float* __restrict__ B, int ldb,
                                                     int col0, int ncols, float sigma_f2,
-                                                    float* __restrict__ out, int ldo) {
+                                                    float* __restrict__ out, int ldo,
+                                                    int qchunk, size_t part_stride) {
     __shared__ float4 xo[BP_CHUNK];
     __shared__ float4 Bs[BP_CHUNK][4][BP_CB / 4];      // [q][g][k/4], columns g + 4k
     __shared__ float Kt[BP_ROWS][BP_CHUNK + 1];
@@ -36,8 +37,11 @@ __global__ __launch_bounds__(256) void k_block_fp32(const float4* __restrict__ X
 #pragma unroll
     for (int k = 0; k < BP_CB; ++k) acc[k] = 0.0f;
 
-    for (int q0 = 0; q0 < m; q0 += BP_CHUNK) {
-        const int qn = min(BP_CHUNK, m - q0);
+    // observation range of this split: [blockIdx.y qchunk, min(m, (blockIdx.y + 1) qchunk))
+    const int qend = min(m, (int)(blockIdx.y + 1) * qchunk);
+    out += blockIdx.y * part_stride;
+    for (int q0 = blockIdx.y * qchunk; q0 < qend; q0 += BP_CHUNK) {
+        const int qn = min(BP_CHUNK, qend - q0);
         __syncthreads();
         if (tid < BP_CHUNK) xo[tid] = Xo[q0 + min(tid, qn - 1)];
         // B chunk: qn rows x ncols columns into the [q][g][k] layout (zero padded)
@@ -99,7 +103,8 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
                                                     const __bf16* __restrict__ Bth,
                                                     const __bf16* __restrict__ Btl, int ldbt,
                                                     int tile0, int ncols, float sigma_f2,
-                                                    float* __restrict__ out, int ldo) {
+                                                    float* __restrict__ out, int ldo,
+                                                    int qchunk, size_t part_stride) {
     __shared__ float4 xo[MF_KC];
     __shared__ bf16x8 bh[NT * 32][MF_KC / 8 + 1];
     __shared__ bf16x8 bl[X3 ? NT * 32 : 1][MF_KC / 8 + 1];
@@ -112,7 +117,10 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
     for (int c = 0; c < NT; ++c)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[c][i] = 0.0f;
-    for (int q0 = 0; q0 < mp; q0 += MF_KC) {
+    // observation range of this split (qchunk a multiple of MF_KC)
+    const int qend = min(mp, (int)(blockIdx.y + 1) * qchunk);
+    out += blockIdx.y * part_stride;
+    for (int q0 = blockIdx.y * qchunk; q0 < qend; q0 += MF_KC) {
         __syncthreads();
         if (threadIdx.x < MF_KC) xo[threadIdx.x] = Xo[q0 + threadIdx.x];
         for (int e = threadIdx.x; e < NT * 32 * (MF_KC / 8); e += 256) {
@@ -163,11 +171,12 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
 template <int NU2, int DIST, bool X3>
 static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const float4* Xo,
                               int mp, const __bf16* Bth, const __bf16* Btl, int ldbt,
-                              int ncols, float sigma_f2, float* out, int ldo, hipStream_t st) {
-    const dim3 grid((n + MF_ROWS - 1) / MF_ROWS), block(256);
+                              int ncols, float sigma_f2, float* out, int ldo, int nsplit,
+                              int qchunk, size_t part_stride, hipStream_t st) {
+    const dim3 grid((n + MF_ROWS - 1) / MF_ROWS, nsplit), block(256);
 #define CAKF_MF(NTV)                                                                       \
     hipLaunchKernelGGL((k_block_mfma<NU2, DIST, NTV, X3>), grid, block, 0, st, Xs, n, Xo, mp, \
-                       Bth, Btl, ldbt, tile0, ncols, sigma_f2, out, ldo)
+                       Bth, Btl, ldbt, tile0, ncols, sigma_f2, out, ldo, qchunk, part_stride)
     switch (nt) {
         case 1: CAKF_MF(1); break;
         case 2: CAKF_MF(2); break;
@@ -193,35 +202,77 @@ __global__ void k_split_bt(const float* __restrict__ B, int mp, int ldb, int bco
     }
 }
 
+// Sum of the nsplit partial products part[s] (n x ldp, s-major) into out (fixed order).
+__global__ void k_split_sum(const float* __restrict__ part, int nsplit, size_t stride, int n,
+                            int ncols, int ldp, float* __restrict__ out, int ldo) {
+    const size_t total = (size_t)n * ncols;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int row = (int)(e / ncols), col = (int)(e % ncols);
+        const float* p = part + (size_t)row * ldp + col;
+        float v = 0.0f;
+        for (int s = 0; s < nsplit; ++s) v += p[s * stride];
+        out[(size_t)row * ldo + col] = v;
+    }
+}
+
+int block_product_splits(int n, int mp, int bcols, size_t part_elems) {
+    // enough workgroups to fill the 256 CUs several times over (about 1024), at least 512
+    // observations per range, within the partial buffer
+    const int rowblocks = (n + MF_ROWS - 1) / MF_ROWS;
+    if (rowblocks >= 256) return 1;     // the row blocks alone fill the chip
+    int ns = std::max(1, 1024 / std::max(rowblocks, 1));
+    ns = std::min(ns, std::max(1, mp / 512));
+    const size_t per = (size_t)n * (size_t)bcols;
+    while (ns > 1 && (size_t)ns * per > part_elems) --ns;
+    return ns;
+}
+
 void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
                           const float4* Xo, int m, int mp, const float* B, int ldb, int bcols,
                           __bf16* Bth, __bf16* Btl, float sigma_f2, float* out, int ldo,
-                          hipStream_t st) {
+                          hipStream_t st, int nsplit, float* part) {
+    // With nsplit > 1 the observation axis is cut into nsplit ranges (multiples of 512
+    // observations), each range's product goes to part (n x bcols per range) and the ranges
+    // are summed into out afterwards.
+    if (nsplit < 1 || !part) nsplit = 1;
+    const int qchunk = nsplit > 1 ? ((mp + 511) / 512 + nsplit - 1) / nsplit * 512 : mp;
+    float* dst = nsplit > 1 ? part : out;
+    const int ldd = nsplit > 1 ? bcols : ldo;
+    const size_t stride = nsplit > 1 ? (size_t)n * bcols : 0;
     if (prec == 0) {
         const int blocks = (n + BP_ROWS - 1) / BP_ROWS;
         for (int c0 = 0; c0 < bcols; c0 += BP_COLS) {
             const int nc = std::min(BP_COLS, bcols - c0);
             CAKF_DISPATCH_KERNEL(nu2, dist,
-                hipLaunchKernelGGL((k_block_fp32<NU2, DIST>), dim3(blocks), dim3(256), 0, st, Xs,
-                                   n, Xo, m, B, ldb, c0, nc, sigma_f2, out, ldo));
+                hipLaunchKernelGGL((k_block_fp32<NU2, DIST>), dim3(blocks, nsplit), dim3(256), 0,
+                                   st, Xs, n, Xo, m, B, ldb, c0, nc, sigma_f2, dst + c0, ldd,
+                                   nsplit > 1 ? qchunk : m, stride));
         }
-        return;
+    } else {
+        const int ntiles = (bcols + 31) / 32;
+        const size_t total = (size_t)mp * ntiles * 32;
+        hipLaunchKernelGGL(k_split_bt, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
+                           dim3(256), 0, st, B, mp, ldb, bcols, ntiles * 32, Bth, Btl);
+        for (int t0 = 0; t0 < ntiles; t0 += 5) {
+            const int nt = std::min(5, ntiles - t0);
+            if (prec == 2) {
+                CAKF_DISPATCH_KERNEL(nu2, dist,
+                    (launch_mfma_tiles<NU2, DIST, true>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp,
+                                                        bcols, sigma_f2, dst, ldd, nsplit,
+                                                        qchunk, stride, st)));
+            } else {
+                CAKF_DISPATCH_KERNEL(nu2, dist,
+                    (launch_mfma_tiles<NU2, DIST, false>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp,
+                                                         bcols, sigma_f2, dst, ldd, nsplit,
+                                                         qchunk, stride, st)));
+            }
+        }
     }
-    const int ntiles = (bcols + 31) / 32;
-    const size_t total = (size_t)mp * ntiles * 32;
-    hipLaunchKernelGGL(k_split_bt, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
-                       dim3(256), 0, st, B, mp, ldb, bcols, ntiles * 32, Bth, Btl);
-    for (int t0 = 0; t0 < ntiles; t0 += 5) {
-        const int nt = std::min(5, ntiles - t0);
-        if (prec == 2) {
-            CAKF_DISPATCH_KERNEL(nu2, dist,
-                (launch_mfma_tiles<NU2, DIST, true>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp, bcols,
-                                                    sigma_f2, out, ldo, st)));
-        } else {
-            CAKF_DISPATCH_KERNEL(nu2, dist,
-                (launch_mfma_tiles<NU2, DIST, false>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp, bcols,
-                                                     sigma_f2, out, ldo, st)));
-        }
+    if (nsplit > 1) {
+        const size_t total = (size_t)n * bcols;
+        hipLaunchKernelGGL(k_split_sum, dim3((int)std::min<size_t>((total + 255) / 256, 4096)),
+                           dim3(256), 0, st, part, nsplit, stride, n, bcols, bcols, out, ldo);
     }
 }
 

@@ -108,11 +108,14 @@ struct cakf_ctx {
     int gspart_blocks;
     float *gQb, *gMob, *gZr, *gCc;
     double *gW64, *gSr64, *gBb64, *gG1, *gG2, *gX1, *gX2, *gpart, *gacc;
+    // partial products of block products split along the observation axis
+    float* bpart;
+    size_t bpart_elems;
     // block-residual policy (allocated when cfg.policy == CAKF_POLICY_BLOCK)
     int bmax, ldz;
-    double* bS64;   // FP64 copy of the actions (mpmax x imax)
-    double* bZ64;   // [Ghat S_round | S_round | r0] in FP64 (mpmax x ldz)
-    double* bG;     // S^T [Ghat S_round | S_round | r0] (imax x ldz)
+    double* bpart64;  // slab partials of the round's Gram product
+    float* bpart32;   // slab partials of Mo^T S_round
+    double* bG;       // S^T [U_r | S_r | V_r | r0] of the round (imax x ldz)
 };
 
 namespace {
@@ -165,7 +168,7 @@ static void free_all(cakf_ctx* c) {
                     c->sm_WR, c->sm_Bth, c->sm_Btl, c->gMb[0], c->gMb[1], c->gmb, c->gYb,
                     c->gBq, c->gBb, c->gbpart, c->gspart, c->gQb, c->gMob, c->gZr, c->gCc,
                     c->gW64, c->gSr64, c->gBb64, c->gG1, c->gG2, c->gX1, c->gX2, c->gpart,
-                    c->gacc, c->bS64, c->bZ64, c->bG};
+                    c->gacc, c->bpart64, c->bpart32, c->bG, c->bpart};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -325,11 +328,27 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         rc |= dalloc(&c->gpart, (n + 3) / 4);
         rc |= dalloc(&c->gacc, 4);
     }
+    {
+        // Block products with few row blocks are split along the observation axis (see
+        // launch_block_product); size their partial buffer for the largest split, capped.
+        const size_t unlimited = ~(size_t)0, cap = (size_t)32 << 20;
+        auto need_of = [&](int rows, int mp, int cols) -> size_t {
+            const int ns = block_product_splits(rows, mp, cols, unlimited);
+            return ns > 1 ? (size_t)ns * rows * cols : 0;
+        };
+        size_t need = need_of(c->n, c->mpmax, c->bp);
+        if (cfg->policy == CAKF_POLICY_BLOCK)
+            need = std::max(need, need_of(c->mpmax, c->mpmax, cfg->block_actions));
+        if (cfg->smoother)
+            need = std::max(need, need_of(c->n, round_up(c->n, SYM_TILE), round_up(1 + c->r, 32)));
+        c->bpart_elems = std::min(need, cap);
+        if (c->bpart_elems) rc |= dalloc(&c->bpart, c->bpart_elems);
+    }
     if (cfg->policy == CAKF_POLICY_BLOCK) {
         c->bmax = cfg->block_actions;
-        c->ldz = 2 * c->bmax + 1;
-        rc |= dalloc(&c->bS64, (size_t)c->mpmax * c->imax);
-        rc |= dalloc(&c->bZ64, (size_t)c->mpmax * c->ldz);
+        c->ldz = 3 * c->bmax + 1;
+        rc |= dalloc(&c->bpart64, round_products_elems(c->mmax, c->imax, c->ldz));
+        rc |= dalloc(&c->bpart32, round_products_elems(c->mmax, c->r, c->bmax));
         rc |= dalloc(&c->bG, (size_t)c->imax * c->ldz);
     }
     if (rc) {
@@ -476,8 +495,8 @@ static rocblas_status dgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N,
 // The action loop of the block-residual policy: rounds of bt actions.  A round splits the
 // current residual over bt observation groups (the new action columns), multiplies them by
 // the prior covariance of the observed points in one block product, subtracts the low-rank
-// part with two GEMMs, and forms all Gram columns of the round with one FP64 GEMM,
-//     G = S^T [Ghat S_round | S_round | r0]   (rows: every action so far),
+// part (Mo^T S_round, then Mo times that), and forms all Gram columns of the round in one
+// FP64-accumulated product G = S^T [U_r | S_r | V_r | r0] (rows: every action so far),
 // from which the incremental Cholesky step takes one column per action.
 static int block_rounds(cakf_ctx* c, const ObsDims& d, int imax, hipStream_t st) {
     const int nu2 = c->cfg.kernel, dist = c->cfg.dist, m = d.m;
@@ -487,28 +506,32 @@ static int block_rounds(cakf_ctx* c, const ObsDims& d, int imax, hipStream_t st)
         launch_block_residual(c->U, c->V, c->S, c->r0, c->beta, noise, d, j0, bt, c->ls, st);
         launch_block_product(nu2, dist, c->cfg.prec, c->Xo, m, c->Xo, m, d.mp, c->S + j0,
                              d.imax, bt, c->Bth, c->Btl, (float)c->cfg.signal_var, c->U + j0,
-                             d.imax, st);
+                             d.imax, st, block_product_splits(m, d.mp, bt, c->bpart_elems),
+                             c->bpart);
         if (d.rank > 0) {
-            const float one = 1.0f, zero = 0.0f;
             // T[:, j0 + g] = Mo^T s_(j0 + g)   (column-major, ld ldmo)
-            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                                   d.rank, bt, m, &one, c->Mo, c->ldmo, c->S + j0, d.imax,
-                                   &zero, c->T + (size_t)j0 * c->ldmo, c->ldmo));
+            launch_round_mot(c->Mo, c->S, d, j0, bt, c->bpart32, c->T, st);
             // V[:, j0 + g] = Mo T[:, j0 + g]   (row-major rows of V, ld imax)
+            const float one = 1.0f, zero = 0.0f;
             BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none,
                                    bt, m, d.rank, &one, c->T + (size_t)j0 * c->ldmo, c->ldmo,
                                    c->Mo, c->ldmo, &zero, c->V + j0, d.imax));
         }
-        launch_block_pack64(c->U, c->V, c->S, c->r0, noise, d, j0, bt, d.rank > 0 ? 1 : 0,
-                            c->bS64, c->bZ64, c->ldz, st);
-        BLAS_TRY(dgemm_rm(c->blas, true, false, j0 + bt, 2 * bt + 1, m, 1.0, c->bS64, d.imax,
-                          c->bZ64, c->ldz, 0.0, c->bG, c->ldz));
-        for (int g = 0; g < bt; ++g) {
+        // G = S^T [U_r | S_r | V_r | r0] over every action so far
+        launch_round_gram(c->U, c->V, c->S, c->r0, d, j0, bt, c->bpart64, c->bG, c->ldz, st);
+        {
+            // the round's bt Cholesky steps in one launch
             PhaseTimer t(c, CAKF_PHASE_TAIL);
-            launch_tail(nullptr, nullptr, 0, nullptr, d, j0 + g, c->cfg.noise_var,
+            TailDirect td;
+            td.G = c->bG;
+            td.ld = c->ldz;
+            td.uc = 0;
+            td.sc = bt;
+            td.vc = 2 * bt;
+            td.rc = 3 * bt;
+            launch_tail(nullptr, nullptr, 0, nullptr, d, j0, c->cfg.noise_var,
                         c->cfg.resid_tol, c->cfg.pivot_tol, c->Linv, c->LinvT, c->L, c->LSinv,
-                        c->LSinvT, c->alpha, c->beta, c->ls, st, c->bG, c->ldz, g, bt + g,
-                        2 * bt);
+                        c->LSinvT, c->alpha, c->beta, c->ls, st, td, bt);
         }
         j0 += bt;
     }
@@ -612,7 +635,8 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     {
         PhaseTimer t(c, CAKF_PHASE_BLOCK_PRODUCT);
         launch_block_product(nu2, dist, c->cfg.prec, c->Xs, c->n, c->Xo, m, d.mp, c->B, c->bp, b,
-                             c->Bth, c->Btl, (float)c->cfg.signal_var, M + d.rank, c->ldM, st);
+                             c->Bth, c->Btl, (float)c->cfg.signal_var, M + d.rank, c->ldM, st,
+                             block_product_splits(c->n, d.mp, b, c->bpart_elems), c->bpart);
     }
     if (d.rank > 0) {
         const float mone = -1.0f, one = 1.0f;
@@ -850,7 +874,8 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
         PhaseTimer t(c, CAKF_PHASE_BLOCK_PRODUCT);
         launch_block_product(c->cfg.kernel, c->cfg.dist, c->cfg.prec, c->Xs, c->n, c->Xp, c->n,
                              c->np, c->sm_B, c->bps, b, c->sm_Bth, c->sm_Btl,
-                             (float)c->cfg.signal_var, c->sm_Y, c->bps, st);
+                             (float)c->cfg.signal_var, c->sm_Y, c->bps, st,
+                             block_product_splits(c->n, c->np, b, c->bpart_elems), c->bpart);
     }
     // Z = P_k A^T [ws Ws] = Y - M_k (M_k^T Bs)
     HIP_TRY(hipMemcpyAsync(c->sm_Z, c->sm_Y, (size_t)c->n * c->bps * sizeof(float),

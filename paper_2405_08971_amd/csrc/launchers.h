@@ -33,6 +33,15 @@ struct LoopState {
 };
 
 // Shapes shared by the observation-space kernels.
+// Direct mode of the Cholesky step (block-residual rounds): the Gram columns of the
+// actions come ready from a round's product G (ld columns; row l = action l): columns
+// uc + g, sc + g, vc + g hold s_l^T u_g, s_l^T s_g, s_l^T v_g of the round's action g,
+// column rc holds s_l^T r0.  G == nullptr selects the column products of the CG loop.
+struct TailDirect {
+    const double* G = nullptr;
+    int ld = 0, uc = 0, sc = 0, vc = 0, rc = 0;
+};
+
 struct ObsDims {
     int m;        // observations
     int mp;       // m rounded up to SYM_TILE
@@ -71,13 +80,17 @@ void launch_tail(const double* colvec, const double* fupart, int nfu, const doub
                  const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
                  double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
                  double* alpha, double* beta, LoopState* ls, hipStream_t st,
-                 const double* gdir = nullptr, int ldg = 0, int jc = 0, int jq = 0, int jr = 0);
+                 const TailDirect& td = TailDirect{}, int nj = 1);
 void launch_block_residual(const float* U, const float* V, float* S, const float* r0,
                            const double* beta, float noise_var, const ObsDims& d, int j0, int bt,
                            const LoopState* ls, hipStream_t st);
-void launch_block_pack64(const float* U, const float* V, const float* S, const float* r0,
-                         float noise_var, const ObsDims& d, int j0, int bt, int lowrank,
-                         double* S64, double* Z64, int ldz, hipStream_t st);
+// skinny products of a block-policy round (partial buffer: round_products_elems)
+size_t round_products_elems(int m, int P, int Q);
+void launch_round_gram(const float* U, const float* V, const float* S, const float* r0,
+                       const ObsDims& d, int j0, int bt, double* part, double* G, int ldg,
+                       hipStream_t st);
+void launch_round_mot(const float* Mo, const float* S, const ObsDims& d, int j0, int bt,
+                      float* part, float* T, hipStream_t st);
 void launch_next_action(int resid, const float* U, const float* Mo, const float* r0, float* S,
                         float* V, const double* beta, const float* T, float noise_var,
                         const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
@@ -93,7 +106,9 @@ void launch_finish_record(const LoopState* ls, const double* L, const double* Li
 void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
                           const float4* Xo, int m, int mp, const float* B, int ldb, int bcols,
                           __bf16* Bth, __bf16* Btl, float sigma_f2, float* out, int ldo,
-                          hipStream_t st);
+                          hipStream_t st, int nsplit = 1, float* part = nullptr);
+// number of observation-axis splits for a block product of n rows (see launch_block_product)
+int block_product_splits(int n, int mp, int bcols, size_t part_elems);
 
 // ---- truncate.hip
 void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* work,

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
                                                        const double* __restrict__ fupart,
                                                        int nfu,
                                                        const double* __restrict__ ttv,
-                                                       ObsDims d, int j, double noise_var,
+                                                       ObsDims d, int jfirst, double noise_var,
                                                        double resid_tol, double pivot_tol,
                                                        double* __restrict__ Linv,
                                                        double* __restrict__ LinvT,
@@ -469,157 +469,165 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
                                                        double* __restrict__ alpha,
                                                        double* __restrict__ beta,
                                                        LoopState* __restrict__ ls,
-                                                       const double* __restrict__ gdir,
-                                                       int ldg, int jc, int jq, int jr) {
+                                                       TailDirect td, int nj) {
     __shared__ double Ccol[256], Qcol[256], lrow[256], lsrow[256], nrow[256], alph[256];
     __shared__ double red[3][TAIL_THREADS / 64];
     const int tid = threadIdx.x;
     if (ls->stop) return;
     const int ld = d.imax;
-    const int J = j + 1;
-    // 1. column j: u_l^T s_j (l < j) and s_l^T s_j (l <= j) from the column products,
-    //    s_j^T u_j from form_u's partial sums
-    //    (direct mode, gdir != null: the column of C itself, s_l^T Ghat s_j, together
-    //    with s_l^T s_j and r0^T s_j, from columns jc, jq, jr of gdir)
-    double fu = 0.0, cj = 0.0, unused = 0.0;
-    if (!gdir)
-        for (int b = tid; b < nfu; b += TAIL_THREADS) fu += fupart[b];
-    if (tid == 0) cj = gdir ? gdir[(size_t)j * ldg + jr] : colvec[2 * j + 1];
-    double gcol = 0.0, qcol = 0.0, tt = 0.0, al = 0.0;
-    if (tid < J) {
-        if (gdir) {
-            gcol = gdir[(size_t)tid * ldg + jc];
-            qcol = gdir[(size_t)tid * ldg + jq];
-        } else {
-            gcol = tid < j ? colvec[tid] : 0.0;
-            qcol = colvec[j + tid];
-            tt = d.rank > 0 ? ttv[tid] : 0.0;
+    // nj consecutive actions jfirst .. jfirst + nj - 1 (nj > 1 only in direct mode); every
+    // exit below is taken by the whole workgroup and ends the loop with the stop flag set
+    const double* gdir = td.G;
+    for (int g = 0; g < nj; ++g) {
+        const int j = jfirst + g;
+        const int J = j + 1;
+        // 1. column j: u_l^T s_j (l < j) and s_l^T s_j (l <= j) from the column products,
+        //    s_j^T u_j from form_u's partial sums
+        //    (direct mode: s_l^T u_j, s_l^T s_j, s_l^T v_j and s_j^T r0 from columns
+        //    uc + g, sc + g, vc + g and rc of td.G)
+        double fu = 0.0, cj = 0.0, unused = 0.0;
+        if (!gdir)
+            for (int b = tid; b < nfu; b += TAIL_THREADS) fu += fupart[b];
+        if (tid == 0) cj = gdir ? gdir[(size_t)j * td.ld + td.rc] : colvec[2 * j + 1];
+        double gcol = 0.0, qcol = 0.0, tt = 0.0, al = 0.0;
+        if (tid < J) {
+            if (gdir) {
+                const double* row = gdir + (size_t)tid * td.ld;
+                qcol = row[td.sc + g];
+                gcol = row[td.uc + g] + noise_var * qcol - row[td.vc + g];
+            } else {
+                gcol = tid < j ? colvec[tid] : 0.0;
+                qcol = colvec[j + tid];
+                tt = d.rank > 0 ? ttv[tid] : 0.0;
+            }
+            al = tid < j ? alpha[tid] : 0.0;
         }
-        al = tid < j ? alpha[tid] : 0.0;
-    }
-    block_sum3(fu, cj, unused, red);
-    const double c_j = cj;
-    if (tid < J) {
-        const double g = (gdir || tid < j) ? gcol : fu;
-        Ccol[tid] = gdir ? g : g - tt + noise_var * qcol;
-        Qcol[tid] = qcol;
-        alph[tid] = al;
-    }
-    __syncthreads();
-    if (j == 0) {
-        if (tid == 0) ls->q00 = Qcol[0];
-    } else if (resid_tol > 0.0 && Qcol[j] <= resid_tol * resid_tol * ls->q00) {
-        if (tid == 0) ls->stop = 1;
-        return;
-    }
-    // rows of the triangular products: j rows, tpr threads per row
-    const int tpr = j > 0 ? std::min(64, TAIL_THREADS / pow2_at_least(j)) : 1;
-    const int row = tid / tpr, sub = tid % tpr;
-    // 2. l = L^{-1} C[0:j, j] and ls = LS^{-1} Q[0:j, j]
-    {
-        double lk = 0.0, lsk = 0.0;
-        if (row < j) {
-            for (int p0 = sub; p0 <= row; p0 += TAIL_BATCH * tpr) {
-                double a[TAIL_BATCH], b[TAIL_BATCH];
-#pragma unroll
-                for (int u = 0; u < TAIL_BATCH; ++u) {
-                    const int p = p0 + u * tpr;
-                    a[u] = p <= row ? LinvT[(size_t)p * ld + row] : 0.0;
-                    b[u] = p <= row ? LSinvT[(size_t)p * ld + row] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < TAIL_BATCH; ++u) {
-                    const int p = p0 + u * tpr;
-                    if (p <= row) {
-                        lk = __builtin_fma(a[u], Ccol[p], lk);
-                        lsk = __builtin_fma(b[u], Qcol[p], lsk);
+        block_sum3(fu, cj, unused, red);
+        const double c_j = cj;
+        if (tid < J) {
+            const double gv = (gdir || tid < j) ? gcol : fu;
+            Ccol[tid] = gdir ? gv : gv - tt + noise_var * qcol;
+            Qcol[tid] = qcol;
+            alph[tid] = al;
+        }
+        __syncthreads();
+        if (j == 0) {
+            if (tid == 0) ls->q00 = Qcol[0];
+        } else if (resid_tol > 0.0 && Qcol[j] <= resid_tol * resid_tol * ls->q00) {
+            if (tid == 0) ls->stop = 1;
+            return;
+        }
+        // rows of the triangular products: j rows, tpr threads per row
+        const int tpr = j > 0 ? std::min(64, TAIL_THREADS / pow2_at_least(j)) : 1;
+        const int row = tid / tpr, sub = tid % tpr;
+        // 2. l = L^{-1} C[0:j, j] and ls = LS^{-1} Q[0:j, j]
+        {
+            double lk = 0.0, lsk = 0.0;
+            if (row < j) {
+                for (int p0 = sub; p0 <= row; p0 += TAIL_BATCH * tpr) {
+                    double a[TAIL_BATCH], b[TAIL_BATCH];
+    #pragma unroll
+                    for (int u = 0; u < TAIL_BATCH; ++u) {
+                        const int p = p0 + u * tpr;
+                        a[u] = p <= row ? LinvT[(size_t)p * ld + row] : 0.0;
+                        b[u] = p <= row ? LSinvT[(size_t)p * ld + row] : 0.0;
+                    }
+    #pragma unroll
+                    for (int u = 0; u < TAIL_BATCH; ++u) {
+                        const int p = p0 + u * tpr;
+                        if (p <= row) {
+                            lk = __builtin_fma(a[u], Ccol[p], lk);
+                            lsk = __builtin_fma(b[u], Qcol[p], lsk);
+                        }
                     }
                 }
             }
+            lk = group_sum(lk, tpr);
+            lsk = group_sum(lsk, tpr);
+            if (row < j && sub == 0) {
+                lrow[row] = lk;
+                lsrow[row] = lsk;
+            }
         }
-        lk = group_sum(lk, tpr);
-        lsk = group_sum(lsk, tpr);
-        if (row < j && sub == 0) {
-            lrow[row] = lk;
-            lsrow[row] = lsk;
+        __syncthreads();
+        double l2 = 0.0, ls2 = 0.0, la = 0.0;
+        if (tid < j) {
+            l2 = lrow[tid] * lrow[tid];
+            ls2 = lsrow[tid] * lsrow[tid];
+            la = lrow[tid] * alph[tid];
         }
-    }
-    __syncthreads();
-    double l2 = 0.0, ls2 = 0.0, la = 0.0;
-    if (tid < j) {
-        l2 = lrow[tid] * lrow[tid];
-        ls2 = lsrow[tid] * lsrow[tid];
-        la = lrow[tid] * alph[tid];
-    }
-    block_sum3(l2, ls2, la, red);
-    const double d2 = Ccol[j] - l2;
-    const bool finite = isfinite(d2) && isfinite(Ccol[j]);
-    if (!(finite && d2 > pivot_tol * Ccol[j] && d2 > 0.0)) {
+        block_sum3(l2, ls2, la, red);
+        const double d2 = Ccol[j] - l2;
+        const bool finite = isfinite(d2) && isfinite(Ccol[j]);
+        if (!(finite && d2 > pivot_tol * Ccol[j] && d2 > 0.0)) {
+            if (tid == 0) {
+                ls->stop = 1;
+                ls->dropped += 1;
+                if (!finite) ls->nonfinite += 1;
+            }
+            return;
+        }
+        const double dj = sqrt(d2);
+        const double inv_d = 1.0 / dj;
+        const double ds = sqrt(fmax(Qcol[j] - ls2, 1e-300));
+        const double aj = (c_j - la) * inv_d;
+        // 3. new row j of L^{-1} (and of LS^{-1}): -(l^T L^{-1}) / d, 1 / d
+        {
+            double acc = 0.0, accs = 0.0;
+            if (row < j) {
+                for (int k0 = row + sub; k0 < j; k0 += TAIL_BATCH * tpr) {
+                    double a[TAIL_BATCH], b[TAIL_BATCH];
+    #pragma unroll
+                    for (int u = 0; u < TAIL_BATCH; ++u) {
+                        const int k = k0 + u * tpr;
+                        a[u] = k < j ? Linv[(size_t)k * ld + row] : 0.0;
+                        b[u] = k < j ? LSinv[(size_t)k * ld + row] : 0.0;
+                    }
+    #pragma unroll
+                    for (int u = 0; u < TAIL_BATCH; ++u) {
+                        const int k = k0 + u * tpr;
+                        if (k < j) {
+                            acc = __builtin_fma(lrow[k], a[u], acc);
+                            accs = __builtin_fma(lsrow[k], b[u], accs);
+                        }
+                    }
+                }
+            }
+            acc = group_sum(acc, tpr);
+            accs = group_sum(accs, tpr);
+            if (row < j && sub == 0) {
+                const double v = -acc * inv_d, vs = -accs / ds;
+                Linv[(size_t)j * ld + row] = v;
+                LinvT[(size_t)row * ld + j] = v;
+                LSinv[(size_t)j * ld + row] = vs;
+                LSinvT[(size_t)row * ld + j] = vs;
+                L[(size_t)j * ld + row] = lrow[row];
+                nrow[row] = v;
+            }
+        }
         if (tid == 0) {
-            ls->stop = 1;
-            ls->dropped += 1;
-            if (!finite) ls->nonfinite += 1;
+            Linv[(size_t)j * ld + j] = inv_d;
+            LinvT[(size_t)j * ld + j] = inv_d;
+            LSinv[(size_t)j * ld + j] = 1.0 / ds;
+            LSinvT[(size_t)j * ld + j] = 1.0 / ds;
+            L[(size_t)j * ld + j] = dj;
+            nrow[j] = inv_d;
+            alpha[j] = aj;
+            ls->logdet_c += 2.0 * log(dj);
+            ls->logdet_s += 2.0 * log(ds);
+            ls->alpha2 += aj * aj;
+            ls->i_eff = J;
+            ls->loglik = -0.5 * ((double)J * 1.8378770664093453 + ls->logdet_c - ls->logdet_s +
+                                 ls->alpha2);
         }
-        return;
-    }
-    const double dj = sqrt(d2);
-    const double inv_d = 1.0 / dj;
-    const double ds = sqrt(fmax(Qcol[j] - ls2, 1e-300));
-    const double aj = (c_j - la) * inv_d;
-    // 3. new row j of L^{-1} (and of LS^{-1}): -(l^T L^{-1}) / d, 1 / d
-    {
-        double acc = 0.0, accs = 0.0;
-        if (row < j) {
-            for (int k0 = row + sub; k0 < j; k0 += TAIL_BATCH * tpr) {
-                double a[TAIL_BATCH], b[TAIL_BATCH];
-#pragma unroll
-                for (int u = 0; u < TAIL_BATCH; ++u) {
-                    const int k = k0 + u * tpr;
-                    a[u] = k < j ? Linv[(size_t)k * ld + row] : 0.0;
-                    b[u] = k < j ? LSinv[(size_t)k * ld + row] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < TAIL_BATCH; ++u) {
-                    const int k = k0 + u * tpr;
-                    if (k < j) {
-                        acc = __builtin_fma(lrow[k], a[u], acc);
-                        accs = __builtin_fma(lsrow[k], b[u], accs);
-                    }
-                }
-            }
+        __syncthreads();
+        // 4. beta = L^{-T} alpha: the previous beta plus alpha_j times row j of L^{-1}
+        if (tid < J) {
+            const double prev = tid < j ? beta[tid] : 0.0;
+            beta[tid] = __builtin_fma(aj, nrow[tid], prev);
         }
-        acc = group_sum(acc, tpr);
-        accs = group_sum(accs, tpr);
-        if (row < j && sub == 0) {
-            const double v = -acc * inv_d, vs = -accs / ds;
-            Linv[(size_t)j * ld + row] = v;
-            LinvT[(size_t)row * ld + j] = v;
-            LSinv[(size_t)j * ld + row] = vs;
-            LSinvT[(size_t)row * ld + j] = vs;
-            L[(size_t)j * ld + row] = lrow[row];
-            nrow[row] = v;
-        }
-    }
-    if (tid == 0) {
-        Linv[(size_t)j * ld + j] = inv_d;
-        LinvT[(size_t)j * ld + j] = inv_d;
-        LSinv[(size_t)j * ld + j] = 1.0 / ds;
-        LSinvT[(size_t)j * ld + j] = 1.0 / ds;
-        L[(size_t)j * ld + j] = dj;
-        nrow[j] = inv_d;
-        alpha[j] = aj;
-        ls->logdet_c += 2.0 * log(dj);
-        ls->logdet_s += 2.0 * log(ds);
-        ls->alpha2 += aj * aj;
-        ls->i_eff = J;
-        ls->loglik = -0.5 * ((double)J * 1.8378770664093453 + ls->logdet_c - ls->logdet_s +
-                             ls->alpha2);
-    }
-    __syncthreads();
-    // 4. beta = L^{-T} alpha: the previous beta plus alpha_j times row j of L^{-1}
-    if (tid < J) {
-        const double prev = tid < j ? beta[tid] : 0.0;
-        beta[tid] = __builtin_fma(aj, nrow[tid], prev);
+        // the next action reads this one's rows of L^{-1}, alpha_j and beta
+        __syncthreads();
     }
 }
 
@@ -627,10 +635,10 @@ void launch_tail(const double* colvec, const double* fupart, int nfu, const doub
                  const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
                  double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
                  double* alpha, double* beta, LoopState* ls, hipStream_t st,
-                 const double* gdir, int ldg, int jc, int jq, int jr) {
+                 const TailDirect& td, int nj) {
     hipLaunchKernelGGL(k_tail, dim3(1), dim3(TAIL_THREADS), 0, st, colvec, fupart, nfu, ttv, d,
                        j, noise_var, resid_tol, pivot_tol, Linv, LinvT, L, LSinv, LSinvT, alpha,
-                       beta, ls, gdir, ldg, jc, jq, jr);
+                       beta, ls, td, td.G ? nj : 1);
 }
 
 // ---------------------------------------------------------------------- next_action
@@ -874,38 +882,171 @@ void launch_block_residual(const float* U, const float* V, float* S, const float
                        beta, noise_var, d, j0, bt, ls);
 }
 
-// FP64 operands of a round's Gram columns, rows p < m: S64[p, j0 + g] = S[p, j0 + g] and
-// Z64[p, :] = [z_g (bt) | s_g (bt) | r0], z = U - V + noise_var S (= Ghat s), g < bt.
-__global__ void k_block_pack64(const float* __restrict__ U, const float* __restrict__ V,
-                               const float* __restrict__ S, const float* __restrict__ r0,
-                               float noise_var, ObsDims d, int j0, int bt, int lowrank,
-                               double* __restrict__ S64, double* __restrict__ Z64, int ldz) {
-    const size_t total = (size_t)d.m * (2 * bt + 1);
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int p = (int)(e / (2 * bt + 1)), c = (int)(e % (2 * bt + 1));
-        double v;
-        if (c < bt) {
-            const size_t o = (size_t)p * d.imax + j0 + c;
-            v = (double)U[o] + (double)noise_var * (double)S[o] - (lowrank ? (double)V[o] : 0.0);
-        } else if (c < 2 * bt) {
-            const size_t o = (size_t)p * d.imax + j0 + (c - bt);
-            v = (double)S[o];
-            S64[(size_t)p * d.imax + j0 + (c - bt)] = v;
-        } else {
-            v = (double)r0[p];
+// Skinny products of a round, C (P x Q) = sum over the observation rows p of
+// A[p, c] B[p, q] with few columns and m rows: the rows are cut into slabs of ATB_RB, each
+// workgroup forms one slab's products for 64 columns of A and 64 of B (FP32 operands
+// staged in LDS, accumulation in Acc), and a second kernel sums the slabs in a fixed
+// order.  Two instances:
+//   Gram:  A = S[:, 0:P] (all actions so far), B = [U_r | S_r | V_r | r0] over the round's
+//          columns r (FP64 accumulation; C[l, q] then gives s_l^T Ghat s_g =
+//          s_l^T u_g + noise_var s_l^T s_g - s_l^T v_g, s_l^T s_g and s_l^T r0);
+//   Mo^T:  A = Mo (P = rank), B = S_r (FP32 accumulation), C = T[:, r].
+constexpr int ATB_RB = 64;    // rows per slab (one LDS chunk)
+constexpr int ATB_PC = 64;    // columns of A per workgroup
+constexpr int ATB_LD = ATB_RB * ATB_PC / 256;   // elements of A each thread loads
+
+struct RowsA {
+    const float* A;
+    int ld;
+    __device__ float operator()(int p, int c) const { return A[(size_t)p * ld + c]; }
+};
+struct RoundGramB {
+    const float *U, *S, *V, *r0;
+    int ld, j0, bt, lowrank;
+    __device__ float operator()(int p, int q) const {
+        const size_t o = (size_t)p * ld + j0;
+        if (q < bt) return U[o + q];
+        if (q < 2 * bt) return S[o + q - bt];
+        if (q < 3 * bt) return lowrank ? V[o + q - 2 * bt] : 0.0f;
+        return r0[p];
+    }
+};
+
+__device__ __forceinline__ float fma_acc(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fma_acc(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+}
+
+// QC columns of B per workgroup (16, 32 or 64; the smallest that holds Q, else 64 and
+// more workgroups along z): thread (cl, qg) accumulates C[c0 + cl, q0 + qg + 4 k].
+template <typename Acc, int QC, class LA, class LB>
+__global__ __launch_bounds__(256) void k_atb_partial(LA la, LB lb, int m, int P, int Q,
+                                                     Acc* __restrict__ part) {
+    constexpr int BLD = ATB_RB * QC / 256;      // elements of B each thread loads
+    __shared__ float As[ATB_RB][ATB_PC + 1];
+    __shared__ float Bs[ATB_RB][QC + 1];
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.y * ATB_PC, q0 = blockIdx.z * QC;
+    const int p0 = blockIdx.x * ATB_RB;
+    const int cl = tid & 63, qg = tid >> 6;
+    // all of the slab's loads are issued before any of them is used
+    float av[ATB_LD], bv[BLD];
+#pragma unroll
+    for (int u = 0; u < ATB_LD; ++u) {
+        const int p = p0 + u * 4 + qg;
+        av[u] = (p < m && c0 + cl < P) ? la(p, c0 + cl) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < BLD; ++u) {
+        const int e = u * 256 + tid, r = e / QC, q = e % QC, p = p0 + r;
+        bv[u] = (p < m && q0 + q < Q) ? lb(p, q0 + q) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < ATB_LD; ++u) As[u * 4 + qg][cl] = av[u];
+#pragma unroll
+    for (int u = 0; u < BLD; ++u) {
+        const int e = u * 256 + tid;
+        Bs[e / QC][e % QC] = bv[u];
+    }
+    __syncthreads();
+    Acc acc[QC / 4];
+#pragma unroll
+    for (int k = 0; k < QC / 4; ++k) acc[k] = Acc(0);
+#pragma unroll 4
+    for (int r = 0; r < ATB_RB; ++r) {
+        const Acc a = (Acc)As[r][cl];
+#pragma unroll
+        for (int k = 0; k < QC / 4; ++k) acc[k] = fma_acc(a, (Acc)Bs[r][qg + 4 * k], acc[k]);
+    }
+    const int c = c0 + cl;
+    if (c < P) {
+        Acc* out = part + ((size_t)blockIdx.x * P + c) * Q;
+#pragma unroll
+        for (int k = 0; k < QC / 4; ++k) {
+            const int q = q0 + qg + 4 * k;
+            if (q < Q) out[q] = acc[k];
         }
-        Z64[(size_t)p * ldz + c] = v;
     }
 }
 
-void launch_block_pack64(const float* U, const float* V, const float* S, const float* r0,
-                         float noise_var, const ObsDims& d, int j0, int bt, int lowrank,
-                         double* S64, double* Z64, int ldz, hipStream_t st) {
-    const size_t total = (size_t)d.m * (2 * bt + 1);
-    const int blocks = (int)std::min<size_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_block_pack64, dim3(blocks), dim3(256), 0, st, U, V, S, r0, noise_var, d,
-                       j0, bt, lowrank, S64, Z64, ldz);
+template <typename Acc, class LA, class LB>
+static void launch_atb_partial(LA la, LB lb, int m, int P, int Q, Acc* part, hipStream_t st) {
+    const int nslab = (m + ATB_RB - 1) / ATB_RB, pc = (P + ATB_PC - 1) / ATB_PC;
+    if (Q <= 16)
+        hipLaunchKernelGGL((k_atb_partial<Acc, 16, LA, LB>), dim3(nslab, pc, 1), dim3(256), 0,
+                           st, la, lb, m, P, Q, part);
+    else if (Q <= 32)
+        hipLaunchKernelGGL((k_atb_partial<Acc, 32, LA, LB>), dim3(nslab, pc, 1), dim3(256), 0,
+                           st, la, lb, m, P, Q, part);
+    else
+        hipLaunchKernelGGL((k_atb_partial<Acc, 64, LA, LB>), dim3(nslab, pc, (Q + 63) / 64),
+                           dim3(256), 0, st, la, lb, m, P, Q, part);
+}
+
+// C[c, q] = sum over the slabs of part, written to G[c * ldg + q] (FP64) or, for the
+// Mo^T instance, to T[(j0 + q) * ldt + c] (FP32, column-major).  A workgroup takes 64
+// consecutive outputs; wave w sums the w-th quarter of the slabs (8 loads in flight, added
+// in slab order) and the four quarters are added in order: a fixed summation order.
+template <typename Acc, bool TOUT>
+__global__ __launch_bounds__(256) void k_atb_reduce(const Acc* __restrict__ part, int nslab,
+                                                    int P, int Q, double* __restrict__ G,
+                                                    int ldg, float* __restrict__ T, int ldt,
+                                                    int j0) {
+    __shared__ Acc quarter[4][64];
+    const int total = P * Q;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const int per = (nslab + 3) / 4;
+    const int b0 = w * per, b1 = min(nslab, b0 + per);
+    Acc v = Acc(0);
+    if (e < total) {
+        for (int b = b0; b < b1; b += 8) {
+            Acc x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                x[u] = b + u < b1 ? part[(size_t)(b + u) * total + e] : Acc(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v += x[u];
+        }
+    }
+    quarter[w][lane] = v;
+    __syncthreads();
+    if (w == 0 && e < total) {
+        const Acc sum = ((quarter[0][lane] + quarter[1][lane]) + quarter[2][lane]) +
+                        quarter[3][lane];
+        const int c = e / Q, q = e % Q;
+        if constexpr (TOUT) T[(size_t)(j0 + q) * ldt + c] = (float)sum;
+        else G[(size_t)c * ldg + q] = (double)sum;
+    }
+}
+
+size_t round_products_elems(int m, int P, int Q) {
+    return (size_t)((m + ATB_RB - 1) / ATB_RB) * P * Q;
+}
+
+void launch_round_gram(const float* U, const float* V, const float* S, const float* r0,
+                       const ObsDims& d, int j0, int bt, double* part, double* G, int ldg,
+                       hipStream_t st) {
+    const int P = j0 + bt, Q = 3 * bt + 1;
+    const int nslab = (d.m + ATB_RB - 1) / ATB_RB;
+    launch_atb_partial<double>(RowsA{S, d.imax},
+                               RoundGramB{U, S, V, r0, d.imax, j0, bt, d.rank > 0 ? 1 : 0}, d.m,
+                               P, Q, part, st);
+    const int blocks = (P * Q + 63) / 64;
+    hipLaunchKernelGGL((k_atb_reduce<double, false>), dim3(blocks), dim3(256), 0, st, part,
+                       nslab, P, Q, G, ldg, nullptr, 0, 0);
+}
+
+void launch_round_mot(const float* Mo, const float* S, const ObsDims& d, int j0, int bt,
+                      float* part, float* T, hipStream_t st) {
+    const int P = d.rank, Q = bt;
+    const int nslab = (d.m + ATB_RB - 1) / ATB_RB;
+    launch_atb_partial<float>(RowsA{Mo, d.ldmo}, RowsA{S + j0, d.imax}, d.m, P, Q, part, st);
+    const int blocks = (P * Q + 63) / 64;
+    hipLaunchKernelGGL((k_atb_reduce<float, true>), dim3(blocks), dim3(256), 0, st, part, nslab,
+                       P, Q, nullptr, 0, T, d.ldmo, j0);
 }
 
 // ----------------------------------------------------------------------- build_block

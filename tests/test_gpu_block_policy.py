@@ -73,3 +73,54 @@ def test_block_policy_more_actions_than_observations():
     gpu = gpu_run(cfg, X, steps, [None] * cfg.T, ("block", 3), "fp32")
     errs = compare(cfg, model, recs, gpu)
     _check(errs, END_TO_END_TOL)
+
+
+def test_block_policy_work_precision_against_the_exact_filter():
+    """Work-precision study: the error of the GPU filter (final step, posterior mean and
+    marginal variance) against the exact Kalman filter, for the CG policy and the
+    block-residual policy, as the action budget i grows.  The rank cap holds every
+    column (no truncation), so the projection is the only approximation.  Work is counted
+    in kernel-matrix entries over the observed points per update: the CG loop evaluates
+    half of the symmetric m x m matrix per action, a block round the whole matrix once
+    for its b actions.  Both errors must fall as the budget grows."""
+    from oracle.kalman import kalman_filter
+    from oracle import matern
+
+    budgets = (8, 16, 32, 64)
+    cfg0 = small_config("wp", dim=2, nu2=3, ell=0.2, n=1024, m=256, T=4, noise_var=0.01,
+                        i=max(budgets), r=256)
+    X, steps, _ = inputs(cfg0, seed=15, policy="cg")
+    X64 = X.astype(np.float64)
+    Sigma = matern.gram(X64, X64, cfg0.nu2, cfg0.ell, cfg0.sigma_f2)
+    obs = []
+    for item in steps:
+        idx, y = item
+        H = np.zeros((idx.size, cfg0.n))
+        H[np.arange(idx.size), idx] = 1.0
+        obs.append((H, cfg0.noise_var * np.eye(idx.size), y.astype(np.float64)))
+    exact = kalman_filter(Sigma, cfg0.a, obs)[-1]
+    ex_m, ex_v = exact["m"], np.diag(exact["P"])
+
+    rows = []
+    for policy in ("cg", ("block", 4), ("block", 8)):
+        errs = []
+        for i in budgets:
+            cfg = small_config("wp", dim=2, nu2=3, ell=0.2, n=1024, m=256, T=4,
+                               noise_var=0.01, i=i, r=256)
+            g = gpu_run(cfg, X, steps, [None] * cfg.T, policy, "fp32")[-1]
+            # the computation-aware variance never falls below the exact one (Sec. 3.2:
+            # incomplete computation adds uncertainty)
+            assert np.min(g["var"] - ex_v) >= -1e-4 * cfg.sigma_f2, (policy, i)
+            e_m = rel_mean_err(g["mean"], ex_m)
+            e_v = rel_mean_err(g["var"], ex_v)
+            b = 1 if policy == "cg" else policy[1]
+            entries = (i * cfg.m * cfg.m // 2) if policy == "cg" else \
+                (-(-i // b)) * cfg.m * cfg.m
+            errs.append((e_m, e_v))
+            rows.append((str(policy), i, entries, e_m, e_v))
+        for (m_a, v_a), (m_b, v_b) in zip(errs, errs[1:]):
+            assert m_b <= 1.1 * m_a and v_b <= 1.1 * v_a, (policy, errs)
+        assert errs[-1][0] < 0.5 * errs[0][0] and errs[-1][1] < 0.5 * errs[0][1], (policy, errs)
+    print("\npolicy        i   kernel entries / update   mean rel err   var rel err")
+    for pol, i, ent, e_m, e_v in rows:
+        print(f"{pol:12s} {i:3d}   {ent:22d}   {e_m:12.3e}   {e_v:11.3e}", flush=True)
