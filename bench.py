@@ -49,6 +49,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-next-rows", action="store_true",
                    help="skip the gradient and smoother timings on their own workloads")
+    p.add_argument("--policy", default="cg", choices=["cg", "block"],
+                   help="action policy of the timed run (the headline is cg)")
+    p.add_argument("--block-actions", type=int, default=8)
+    p.add_argument("--no-breakdown", action="store_true",
+                   help="skip the untimed steps with every phase timed (counter passes)")
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 256 MiB device copy (counter calibration)")
@@ -302,7 +307,9 @@ def main():
     inputs = device_inputs(wl, range(1, nsteps + 1))
     torch.cuda.synchronize()
 
-    res = run(cfg, X, inputs, args.warmup, args.steps, args.prec)
+    res = run(cfg, X, inputs, args.warmup, args.steps, args.prec,
+              breakdown=0 if args.no_breakdown else 3, policy=args.policy,
+              block_actions=args.block_actions)
     fp32 = None
     if not args.no_fp32_compare and args.prec != "fp32":
         fp32 = run(cfg, X, inputs, args.warmup, args.steps, "fp32")
@@ -329,8 +336,10 @@ def main():
         "dtype": "fp32" if args.prec == "fp32" else "bf16",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: n={cfg.n} Fibonacci-sphere points, "
-                               f"Matern-{cfg.nu2}/2 chordal, m={cfg.m}, i={cfg.i} CG "
-                               f"actions, r={cfg.r}",
+                               f"Matern-{cfg.nu2}/2 chordal, m={cfg.m}, i={cfg.i} "
+                               + ("CG actions" if args.policy == "cg" else
+                                  f"block-residual actions (b={args.block_actions})")
+                               + f", r={cfg.r}",
                    "block_product": args.prec, "action_loop": "fp32 (fp64 Gram)",
                    "truncation": "fp64 Gram + fp64 eigensolver"},
         "roofline": {"bound": "alu", "kernel": "sym_tiles (action-loop Matern matvec)",
@@ -374,6 +383,7 @@ def main():
             [rec.loglik.item() for rec in res["recs"][args.warmup:]]))
         blk["workload"] = line["config"]["workload"].replace("CG actions",
                                                              "block-residual actions")
+        blk["note"] = "the same inputs as the headline run, timed the same way"
         line["next_rows"]["block_policy"] = blk
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, wl)

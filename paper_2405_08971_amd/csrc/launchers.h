@@ -4,9 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace cakf {
+#include "obs_types.h"
 
-constexpr int SYM_TILE = 128;       // side of the symmetric kernel tiles of the action loop
+namespace cakf {
 
 // Shape of the next_action launch: factor columns per lane (ldmo <= 64 CPL), action columns
 // per lane (imax <= 64 LPL) and rows per wave (fewer when the rows' registers are large).
@@ -18,21 +18,6 @@ constexpr int next_action_blocks(int m, int cpl, int lpl) {
            (4 * next_action_rows_per_wave(cpl, lpl));
 }
 
-// Device-resident scalars of one update's action loop.
-struct LoopState {
-    int stop;          // set once the loop has stopped (budget, tolerance or breakdown)
-    int i_eff;         // actions kept so far
-    int dropped;       // actions dropped on breakdown since the last reset
-    int nonfinite;     // non-finite pivots since the last reset
-    double logdet_c;   // log det S^T Ghat S of the kept actions
-    double logdet_s;   // log det S^T S of the kept actions
-    double alpha2;     // ||L^{-1} S^T r0||^2
-    double q00;        // ||s_0||^2 (CG: ||r0||^2)
-    double loglik;     // projected log-likelihood term of the kept actions
-    int bad_index;     // observation indices outside [0, n) seen by the gather
-};
-
-// Shapes shared by the observation-space kernels.
 // Direct mode of the Cholesky step (block-residual rounds): the Gram columns of the
 // actions come ready from a round's product G (ld columns; row l = action l): columns
 // uc + g, sc + g, vc + g hold s_l^T u_g, s_l^T s_g, s_l^T v_g of the round's action g,
@@ -40,14 +25,6 @@ struct LoopState {
 struct TailDirect {
     const double* G = nullptr;
     int ld = 0, uc = 0, sc = 0, vc = 0, rc = 0;
-};
-
-struct ObsDims {
-    int m;        // observations
-    int mp;       // m rounded up to SYM_TILE
-    int imax;     // action budget; leading dimension of S, U, T and the FP64 triangles
-    int rank;     // columns of the predictive factor
-    int ldmo;     // leading dimension of Mo and T (max_rank rounded up to 8)
 };
 
 // ---- misc.hip
@@ -60,7 +37,7 @@ void launch_marginal_var(const float* M, int n, int ld, int rank, float sigma_f2
 void launch_copy_rows(const float* src, int lds, float* dst, int ldd, int rows, int cols,
                       hipStream_t st);
 
-// ---- obs_loop.hip
+// ---- obs_loop.hip (launch_sym_tiles: sym_tiles.hip)
 void launch_gather(const float4* Xs, int n, const float* mean, const float* M, int ldM,
                    const int32_t* idx, const float* y, const float* given, int cg,
                    const ObsDims& d, float4* Xo, float* r0, float* Mo, float* S, float* U,
