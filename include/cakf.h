@@ -102,6 +102,8 @@ typedef struct {
                                typical 1e-10                                         */
     int prec;               /* CAKF_PREC_* of the block product                      */
     int smoother;           /* nonzero: also allocate the smoother workspace         */
+    int sample_paths;       /* largest number of paths per sampler call, 0..256
+                               (0: no sampler workspace)                              */
     int gradient;           /* nonzero: also allocate the workspace of
                                cakf_loglik_grad (needs max_actions <= 159)           */
     void* stream;           /* hipStream_t for all work; NULL = the null stream      */
@@ -223,6 +225,62 @@ int cakf_smooth_begin(cakf_ctx* ctx, const int32_t* idx, const float* w_obs,
  * output may be NULL.  P_k = Sigma - M_k M_k^T uses the untruncated filter factor. */
 int cakf_smooth_step(cakf_ctx* ctx, const cakf_smooth_input* in, float* mean_out,
                      float* factor_out, int ld_out, float* var_out, int* out_rank);
+
+/* ------------------------------------------------------------ path sampler (App. C)
+ * Joint sample paths of the computation-aware filter and smoother (the CAKF/CAKS
+ * sampler): draws from the prior are pushed through the gains of a recorded filter run,
+ * in the manner of Matheron's rule.  ns <= cfg.sample_paths paths are the columns of
+ * row-major device arrays with leading dimension ns: state arrays n x ns, observation
+ * arrays m x ns.  The random draws are inputs, drawn by the caller:
+ *   x0  ~ N(0, Sigma)              the first state's stationary prior (x_prev at k = 1),
+ *   q_k ~ N(0, (1 - a^2) Sigma)    the process noise of the prediction of step k,
+ *   e_k ~ N(0, I_m)                observation noise in units of sigma (the projected
+ *                                  noise of the paper is eps_k = S_k^T sigma e_k).
+ * Forward, k = 1..T:     x^-_k = a x_{k-1} + q_k,
+ *                        w_k   = H_k^T W_obs L^{-1} S^T (y_k - x^-_k[idx] - sigma e_k),
+ *                        x_k   = x^-_k + P^-_k w_k        (P^-_k = Sigma - M^-_k M^-_k^T).
+ * Backward, k = T-1..1:  ws_T = w_T,  xs_T = x_T,
+ *                        xs_k = x_k + P_k a ws_{k+1}      (P_k = Sigma - M_k M_k^T,
+ *                                                          M_k untruncated),
+ *                        ws_k = w_k + (I - W_k W_k^T P^-_k) a ws_{k+1},  W_k = H^T W_obs.
+ * Without truncation, xs_1..xs_T are distributed as the posterior of the projected
+ * model (conditioning on S_k^T y_k for every k).  Needs cfg.sample_paths >= ns; the m
+ * indices of a step must be distinct.
+ *
+ * Step k's inputs (caller-owned device buffers from the filter run, read only): idx, y,
+ * m (m = 0: a step without data); the record's S (m x max_actions), W_obs
+ * (m x max_actions) and chol_inv (L^{-1}, max_actions x max_actions FP64); the
+ * predictive factor M^-_k = a M^+_{k-1} (n x pred_rank, leading dimension pred_ld). */
+typedef struct {
+    const int32_t* idx;
+    const float* y;
+    int m;
+    const float* S;
+    const float* W_obs;
+    const double* chol_inv;
+    const float* pred_factor;
+    int pred_ld, pred_rank;
+} cakf_sample_input;
+
+/* Forward step k: x_prev = x_{k-1} (x0 at k = 1), q = q_k (n x ns), e = e_k (m x ns;
+ * may be NULL when m = 0) -> x_out = x_k (n x ns; may alias x_prev) and w_obs_out (m x ns),
+ * the message in observation coordinates (w_k = H^T w_obs_out; not written when m = 0). */
+int cakf_sample_forward(cakf_ctx* ctx, int ns, const float* x_prev, const float* q,
+                        const float* e, const cakf_sample_input* in, float* x_out,
+                        float* w_obs_out);
+
+/* ws_out (n x ns) = H^T w_obs: the last step's message, ws_T = w_T (zeros when m = 0). */
+int cakf_sample_lift(cakf_ctx* ctx, int ns, const int32_t* idx, const float* w_obs, int m,
+                     float* ws_out);
+
+/* Backward step k = T-1..1: x = x_k (n x ns) and factor = M_k (untruncated, n x rank,
+ * leading dimension ld) from the forward pass and the filter; in = step k's inputs (y,
+ * S and chol_inv are not read); w_obs = step k's forward message (m x ns);
+ * ws_next = ws_{k+1} (n x ns) -> xs_out = xs_k and ws_out = ws_k (n x ns each; xs_out
+ * may alias x, ws_out may alias ws_next). */
+int cakf_sample_backward(cakf_ctx* ctx, int ns, const float* x, const float* factor, int ld,
+                         int rank, const cakf_sample_input* in, const float* w_obs,
+                         const float* ws_next, float* xs_out, float* ws_out);
 
 /* One filter step as the derivative of the log-likelihood needs it: the step's inputs,
  * its record and the state it passed on, all caller-owned device buffers written by the

@@ -36,7 +36,8 @@ class cakf_config(ctypes.Structure):
         ("policy", ctypes.c_int), ("block_actions", ctypes.c_int),
         ("resid_tol", ctypes.c_double),
         ("pivot_tol", ctypes.c_double), ("prec", ctypes.c_int), ("smoother", ctypes.c_int),
-        ("gradient", ctypes.c_int), ("stream", ctypes.c_void_p),
+        ("sample_paths", ctypes.c_int), ("gradient", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -54,6 +55,15 @@ class cakf_smooth_input(ctypes.Structure):
         ("rank", ctypes.c_int), ("pred_factor", ctypes.c_void_p), ("pred_ld", ctypes.c_int),
         ("pred_rank", ctypes.c_int), ("idx", ctypes.c_void_p), ("w_obs", ctypes.c_void_p),
         ("W_obs", ctypes.c_void_p), ("m", ctypes.c_int),
+    ]
+
+
+class cakf_sample_input(ctypes.Structure):
+    _fields_ = [
+        ("idx", ctypes.c_void_p), ("y", ctypes.c_void_p), ("m", ctypes.c_int),
+        ("S", ctypes.c_void_p), ("W_obs", ctypes.c_void_p), ("chol_inv", ctypes.c_void_p),
+        ("pred_factor", ctypes.c_void_p), ("pred_ld", ctypes.c_int),
+        ("pred_rank", ctypes.c_int),
     ]
 
 
@@ -99,6 +109,11 @@ def lib() -> ctypes.CDLL:
             "cakf_smooth_begin": (i, [vp, vp, vp, vp, i]),
             "cakf_smooth_step": (i, [vp, ctypes.POINTER(cakf_smooth_input), vp, vp, i, vp,
                                      ctypes.POINTER(i)]),
+            "cakf_sample_forward": (i, [vp, i, vp, vp, vp, ctypes.POINTER(cakf_sample_input),
+                                        vp, vp]),
+            "cakf_sample_lift": (i, [vp, i, vp, vp, i, vp]),
+            "cakf_sample_backward": (i, [vp, i, vp, vp, i, i,
+                                         ctypes.POINTER(cakf_sample_input), vp, vp, vp, vp]),
             "cakf_loglik_grad": (i, [vp, i, ctypes.POINTER(cakf_tape_step),
                                      ctypes.POINTER(d)]),
             "cakf_profile_enable": (i, [vp, i]),
@@ -230,3 +245,21 @@ def cakf_loglik_grad(ctx: int, tape) -> list:
     g = (ctypes.c_double * 4)()
     check(lib().cakf_loglik_grad(ctx, len(tape), arr, g), "cakf_loglik_grad")
     return list(g)
+
+
+def cakf_sample_forward(ctx: int, ns: int, x_prev, q, e, inp: cakf_sample_input, x_out,
+                        w_obs_out) -> None:
+    check(lib().cakf_sample_forward(ctx, ns, ptr(x_prev), ptr(q), ptr(e), ctypes.byref(inp),
+                                    ptr(x_out), ptr(w_obs_out)), "cakf_sample_forward")
+
+
+def cakf_sample_lift(ctx: int, ns: int, idx, w_obs, m: int, ws_out) -> None:
+    check(lib().cakf_sample_lift(ctx, ns, ptr(idx), ptr(w_obs), m, ptr(ws_out)),
+          "cakf_sample_lift")
+
+
+def cakf_sample_backward(ctx: int, ns: int, x, factor, ld: int, rank: int,
+                         inp: cakf_sample_input, w_obs, ws_next, xs_out, ws_out) -> None:
+    check(lib().cakf_sample_backward(ctx, ns, ptr(x), ptr(factor), ld, rank, ctypes.byref(inp),
+                                     ptr(w_obs), ptr(ws_next), ptr(xs_out), ptr(ws_out)),
+          "cakf_sample_backward")

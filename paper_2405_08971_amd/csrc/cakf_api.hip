@@ -108,6 +108,11 @@ struct cakf_ctx {
     int gspart_blocks;
     float *gQb, *gMob, *gZr, *gCc;
     double *gW64, *gSr64, *gBb64, *gG1, *gG2, *gX1, *gX2, *gpart, *gacc;
+    // path sampler (allocated when cfg.sample_paths > 0)
+    int sp_ns, bsp;
+    float *sp_B, *sp_W, *sp_Y, *sp_D, *sp_D2, *sp_R, *sp_Z, *sp_Q;
+    __bf16 *sp_Bth, *sp_Btl;
+    float4* sp_Xo;
     // partial products of block products split along the observation axis
     float* bpart;
     size_t bpart_elems;
@@ -168,7 +173,9 @@ static void free_all(cakf_ctx* c) {
                     c->sm_WR, c->sm_Bth, c->sm_Btl, c->gMb[0], c->gMb[1], c->gmb, c->gYb,
                     c->gBq, c->gBb, c->gbpart, c->gspart, c->gQb, c->gMob, c->gZr, c->gCc,
                     c->gW64, c->gSr64, c->gBb64, c->gG1, c->gG2, c->gX1, c->gX2, c->gpart,
-                    c->gacc, c->bpart64, c->bpart32, c->bG, c->bpart};
+                    c->gacc, c->bpart64, c->bpart32, c->bG, c->bpart, c->sp_B,
+                    c->sp_W, c->sp_Y, c->sp_D, c->sp_D2, c->sp_R, c->sp_Z, c->sp_Q, c->sp_Bth,
+                    c->sp_Btl, c->sp_Xo};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -206,6 +213,7 @@ static int validate(const cakf_config* c) {
     if (c->resid_tol < 0 || c->pivot_tol < 0) return CAKF_E_ARG;
     if (c->smoother && (size_t)c->n * (c->max_rank + 1) > ((size_t)1 << 31)) return CAKF_E_ARG;
     if (c->gradient && c->max_actions > 159) return CAKF_E_ARG;
+    if (c->sample_paths < 0 || c->sample_paths > 256) return CAKF_E_ARG;
     return CAKF_OK;
 }
 
@@ -283,11 +291,29 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         rc |= dalloc(&c->tdctr, 1);
         rc |= dalloc(&c->tdabort, 1);
     }
-    if (cfg->smoother) {
+    if (cfg->smoother || cfg->sample_paths > 0) {
         c->np = round_up(c->n, SYM_TILE);
+        rc |= dalloc(&c->Xp, c->np);
+    }
+    if (cfg->sample_paths > 0) {
+        c->sp_ns = cfg->sample_paths;
+        c->bsp = round_up(cfg->sample_paths, 32);
+        const size_t rows = std::max<size_t>(c->np, c->mpmax);
+        rc |= dalloc(&c->sp_B, (size_t)c->mpmax * c->bsp);
+        rc |= dalloc(&c->sp_W, (size_t)c->np * c->bsp);
+        rc |= dalloc(&c->sp_Y, n * c->bsp);
+        rc |= dalloc(&c->sp_D, (size_t)c->mpmax * c->bsp);
+        rc |= dalloc(&c->sp_D2, (size_t)c->mpmax * c->bsp);
+        rc |= dalloc(&c->sp_R, (size_t)c->imax * c->bsp);
+        rc |= dalloc(&c->sp_Z, (size_t)c->imax * c->bsp);
+        rc |= dalloc(&c->sp_Q, (size_t)c->Kmax * c->bsp);
+        rc |= dalloc(&c->sp_Bth, rows * c->bsp);
+        rc |= dalloc(&c->sp_Btl, rows * c->bsp);
+        rc |= dalloc(&c->sp_Xo, c->mpmax);
+    }
+    if (cfg->smoother) {
         c->bps = round_up(1 + c->r, 32);
         c->ldWs = round_up(c->imax + c->r, 4);
-        rc |= dalloc(&c->Xp, c->np);
         rc |= dalloc(&c->sm_ws, n);
         rc |= dalloc(&c->sm_W[0], n * c->ldWs);
         rc |= dalloc(&c->sm_W[1], n * c->ldWs);
@@ -341,6 +367,11 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
             need = std::max(need, need_of(c->mpmax, c->mpmax, cfg->block_actions));
         if (cfg->smoother)
             need = std::max(need, need_of(c->n, round_up(c->n, SYM_TILE), round_up(1 + c->r, 32)));
+        if (cfg->sample_paths > 0) {
+            const int bsp = round_up(cfg->sample_paths, 32);
+            need = std::max(need, need_of(c->n, round_up(c->n, SYM_TILE), bsp));
+            need = std::max(need, need_of(c->n, c->mpmax, bsp));
+        }
         c->bpart_elems = std::min(need, cap);
         if (c->bpart_elems) rc |= dalloc(&c->bpart, c->bpart_elems);
     }
@@ -386,7 +417,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     const int nu2 = cfg->kernel;
     const double scale = 1.4426950408889634 * std::sqrt((double)nu2) / cfg->lengthscale;
     launch_prescale(cfg->X, c->n, cfg->dim, (float)scale, cfg->dist, c->Xs, c->stream);
-    if (cfg->smoother) launch_pad_points(c->Xs, c->n, c->np, c->Xp, c->stream);
+    if (c->Xp) launch_pad_points(c->Xs, c->n, c->np, c->Xp, c->stream);
     if (hipMemsetAsync(c->mean, 0, n * sizeof(float), c->stream) != hipSuccess ||
         hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -927,6 +958,115 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
         c->sm_cur = 1 - c->sm_cur;
         c->sm_rank = K;
     }
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+// ---------------------------------------------------------- path sampler (App. C)
+static int sample_input_ok(const cakf_ctx* c, const cakf_sample_input* in, bool need_record) {
+    if (!in || in->m < 0 || in->m > c->mmax) return 0;
+    if (in->m > 0 && (!in->idx || !in->W_obs)) return 0;
+    if (in->m > 0 && need_record && (!in->y || !in->S || !in->chol_inv)) return 0;
+    if (in->pred_rank < 0 || in->pred_rank > c->Kmax ||
+        (in->pred_rank > 0 && (!in->pred_factor || in->pred_ld < in->pred_rank)))
+        return 0;
+    return 1;
+}
+
+extern "C" int cakf_sample_forward(cakf_ctx* c, int ns, const float* x_prev, const float* q,
+                                   const float* e, const cakf_sample_input* in, float* x_out,
+                                   float* w_obs_out) {
+    if (!c || !c->sp_B || ns < 1 || ns > c->sp_ns || !x_prev || !q || !x_out) return CAKF_E_ARG;
+    if (!sample_input_ok(c, in, true)) return CAKF_E_ARG;
+    if (in->m > 0 && (!e || !w_obs_out)) return CAKF_E_ARG;
+    hipStream_t st = c->stream;
+    const int n = c->n, m = in->m, imax = c->imax, bsp = c->bsp;
+    // x^- = a x_{k-1} + q
+    launch_sample_predict(x_prev, q, (float)c->cfg.ou_coeff, n, ns, ns, x_out, st);
+    if (m == 0) return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+    const int mp = round_up(m, SYM_TILE);
+    // d = y - x^-[idx] - sigma e;  z = L^{-1} S^T d;  wobs = W_obs z (zero padding rows)
+    launch_sample_innov(in->y, in->idx, x_out, ns, e, ns, (float)std::sqrt(c->cfg.noise_var), n,
+                        m, ns, c->sp_D, bsp, st);
+    BLAS_TRY(sgemm_rm(c->blas, true, false, imax, ns, m, 1.0f, in->S, imax, c->sp_D, bsp, 0.0f,
+                      c->sp_R, bsp));
+    launch_sample_solve(in->chol_inv, imax, c->sp_R, ns, bsp, c->sp_Z, st);
+    HIP_TRY(hipMemsetAsync(c->sp_B, 0, (size_t)mp * bsp * sizeof(float), st));
+    BLAS_TRY(sgemm_rm(c->blas, false, false, m, ns, imax, 1.0f, in->W_obs, imax, c->sp_Z, bsp,
+                      0.0f, c->sp_B, bsp));
+    launch_copy_rows(c->sp_B, bsp, w_obs_out, ns, m, ns, st);
+    // x = x^- + sigma_f2 K(X, Xo) wobs - M^- (M^-^T H^T wobs)
+    launch_gather_points(c->Xs, n, in->idx, m, mp, c->sp_Xo, st);
+    launch_block_product(c->cfg.kernel, c->cfg.dist, c->cfg.prec, c->Xs, n, c->sp_Xo, m, mp,
+                         c->sp_B, bsp, ns, c->sp_Bth, c->sp_Btl, (float)c->cfg.signal_var,
+                         c->sp_Y, bsp, st, block_product_splits(n, mp, ns, c->bpart_elems),
+                         c->bpart);
+    launch_add_cols(c->sp_Y, bsp, n, ns, x_out, ns, st);
+    if (in->pred_rank > 0) {
+        HIP_TRY(hipMemsetAsync(c->sp_W, 0, (size_t)n * bsp * sizeof(float), st));
+        launch_sample_scatter(in->idx, n, m, ns, c->sp_B, bsp, nullptr, 0, c->sp_W, bsp, st);
+        BLAS_TRY(sgemm_rm(c->blas, true, false, in->pred_rank, ns, n, 1.0f, in->pred_factor,
+                          in->pred_ld, c->sp_W, bsp, 0.0f, c->sp_Q, bsp));
+        BLAS_TRY(sgemm_rm(c->blas, false, false, n, ns, in->pred_rank, -1.0f, in->pred_factor,
+                          in->pred_ld, c->sp_Q, bsp, 1.0f, x_out, ns));
+    }
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+extern "C" int cakf_sample_lift(cakf_ctx* c, int ns, const int32_t* idx, const float* w_obs,
+                                int m, float* ws_out) {
+    if (!c || !c->sp_B || ns < 1 || ns > c->sp_ns || !ws_out || m < 0 || m > c->mmax)
+        return CAKF_E_ARG;
+    if (m > 0 && (!idx || !w_obs)) return CAKF_E_ARG;
+    hipStream_t st = c->stream;
+    HIP_TRY(hipMemsetAsync(ws_out, 0, (size_t)c->n * ns * sizeof(float), st));
+    launch_sample_scatter(idx, c->n, m, ns, w_obs, ns, nullptr, 0, ws_out, ns, st);
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+extern "C" int cakf_sample_backward(cakf_ctx* c, int ns, const float* x, const float* factor,
+                                    int ld, int rank, const cakf_sample_input* in,
+                                    const float* w_obs, const float* ws_next, float* xs_out,
+                                    float* ws_out) {
+    if (!c || !c->sp_B || ns < 1 || ns > c->sp_ns || !x || !ws_next || !xs_out || !ws_out)
+        return CAKF_E_ARG;
+    if (rank < 0 || rank > c->Kmax || (rank > 0 && (!factor || ld < rank))) return CAKF_E_ARG;
+    if (!sample_input_ok(c, in, false)) return CAKF_E_ARG;
+    if (in->m > 0 && !w_obs) return CAKF_E_ARG;
+    hipStream_t st = c->stream;
+    const int n = c->n, m = in->m, imax = c->imax, bsp = c->bsp;
+    // B = a ws_{k+1} (padded to np rows), Y = sigma_f2 K(X, X) B
+    launch_sample_scale_pad(ws_next, ns, (float)c->cfg.ou_coeff, n, c->np, ns, c->sp_W, bsp, st);
+    launch_block_product(c->cfg.kernel, c->cfg.dist, c->cfg.prec, c->Xs, n, c->Xp, n, c->np,
+                         c->sp_W, bsp, ns, c->sp_Bth, c->sp_Btl, (float)c->cfg.signal_var,
+                         c->sp_Y, bsp, st, block_product_splits(n, c->np, ns, c->bpart_elems),
+                         c->bpart);
+    // xs = x + Y - M (M^T B)
+    if (xs_out != x) launch_copy_rows(x, ns, xs_out, ns, n, ns, st);
+    launch_add_cols(c->sp_Y, bsp, n, ns, xs_out, ns, st);
+    if (rank > 0) {
+        BLAS_TRY(sgemm_rm(c->blas, true, false, rank, ns, n, 1.0f, factor, ld, c->sp_W, bsp, 0.0f,
+                          c->sp_Q, bsp));
+        BLAS_TRY(sgemm_rm(c->blas, false, false, n, ns, rank, -1.0f, factor, ld, c->sp_Q, bsp,
+                          1.0f, xs_out, ns));
+    }
+    if (m > 0) {
+        // Pm = Y - M^- (M^-^T B) in place; WR = W_obs W_obs^T Pm[idx]
+        if (in->pred_rank > 0) {
+            BLAS_TRY(sgemm_rm(c->blas, true, false, in->pred_rank, ns, n, 1.0f, in->pred_factor,
+                              in->pred_ld, c->sp_W, bsp, 0.0f, c->sp_Q, bsp));
+            BLAS_TRY(sgemm_rm(c->blas, false, false, n, ns, in->pred_rank, -1.0f,
+                              in->pred_factor, in->pred_ld, c->sp_Q, bsp, 1.0f, c->sp_Y, bsp));
+        }
+        launch_gather_rows(c->sp_Y, bsp, in->idx, m, n, ns, c->sp_D, bsp, st);
+        BLAS_TRY(sgemm_rm(c->blas, true, false, imax, ns, m, 1.0f, in->W_obs, imax, c->sp_D, bsp,
+                          0.0f, c->sp_R, bsp));
+        BLAS_TRY(sgemm_rm(c->blas, false, false, m, ns, imax, 1.0f, in->W_obs, imax, c->sp_R, bsp,
+                          0.0f, c->sp_D2, bsp));
+    }
+    // ws = B + H^T (wobs - WR)
+    launch_copy_rows(c->sp_W, bsp, ws_out, ns, n, ns, st);
+    if (m > 0)
+        launch_sample_scatter(in->idx, n, m, ns, w_obs, ns, c->sp_D2, bsp, ws_out, ns, st);
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 

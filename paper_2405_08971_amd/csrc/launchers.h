@@ -87,6 +87,25 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
 // number of observation-axis splits for a block product of n rows (see launch_block_product)
 int block_product_splits(int n, int mp, int bcols, size_t part_elems);
 
+// ---- sampler.hip
+void launch_sample_predict(const float* x, const float* q, float a, int n, int ns, int ld,
+                           float* out, hipStream_t st);
+void launch_sample_innov(const float* y, const int32_t* idx, const float* x, int ldx,
+                         const float* e, int lde, float sigma, int n, int m, int ns, float* d,
+                         int ldd, hipStream_t st);
+void launch_sample_solve(const double* Linv, int imax, const float* r, int ns, int ld, float* z,
+                         hipStream_t st);
+void launch_add_cols(const float* Y, int ldy, int n, int ns, float* out, int ldo,
+                     hipStream_t st);
+void launch_sample_scale_pad(const float* in, int ldi, float a, int n, int rows, int ns,
+                             float* out, int ld, hipStream_t st);
+void launch_sample_copy_pad(const float* in, int ldi, int n, int rows, int ns, float* out,
+                            int ld, hipStream_t st);
+void launch_sample_scatter(const int32_t* idx, int n, int m, int ns, const float* v, int ldv,
+                           const float* WR, int ldr, float* out, int ldo, hipStream_t st);
+void launch_gather_points(const float4* Xs, int n, const int32_t* idx, int m, int mp,
+                          float4* Xo, hipStream_t st);
+
 // ---- truncate.hip
 void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* work,
                    size_t work_elems, hipStream_t st);

@@ -42,7 +42,7 @@ class CAKF:
                  policy: str = "cg", block_actions: int = 8, resid_tol: float = 0.0,
                  pivot_tol: float = 1e-10,
                  prec: str = "fp32", smoother: bool = False, gradient: bool = False,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 sample_paths: int = 0, stream: Optional[torch.cuda.Stream] = None):
         if X.dtype != torch.float32 or X.dim() != 2:
             raise ValueError("X must be a float32 (n, dim) device tensor")
         X = X.contiguous()
@@ -56,8 +56,8 @@ class CAKF:
             ou_coeff=ou_coeff, max_obs=max_obs, max_actions=max_actions, max_rank=max_rank,
             policy=L.POLICY[policy], block_actions=block_actions, resid_tol=resid_tol,
             pivot_tol=pivot_tol,
-            prec=L.PREC[prec], smoother=1 if smoother else 0, gradient=1 if gradient else 0,
-            stream=L.stream_handle(stream))
+            prec=L.PREC[prec], smoother=1 if smoother else 0, sample_paths=sample_paths,
+            gradient=1 if gradient else 0, stream=L.stream_handle(stream))
         self._X = X
         self.ctx = L.cakf_create(cfg)
 
@@ -157,6 +157,53 @@ class CAKF:
             out_fac = torch.empty((self.n, ld), dtype=torch.float32, device="cuda")
         rank = L.cakf_smooth_step(self.ctx, inp, out_mean, out_fac, ld, out_var)
         return out_mean, out_var, (out_fac[:, :rank] if want_factor else None)
+
+    # -- path sampler (App. C) -------------------------------------------------------------
+    @staticmethod
+    def _sample_input(idx, y, record: Optional[Record], pred_factor: torch.Tensor):
+        pred_factor = pred_factor.contiguous()
+        m = 0 if idx is None else int(idx.numel())
+        pr = pred_factor.shape[1]
+        return L.cakf_sample_input(
+            idx=L.ptr(idx) if m else None, y=L.ptr(y) if (m and y is not None) else None, m=m,
+            S=L.ptr(record.S) if m else None, W_obs=L.ptr(record.W_obs) if m else None,
+            chol_inv=L.ptr(record.chol_inv) if m else None,
+            pred_factor=L.ptr(pred_factor) if pr else None, pred_ld=max(pr, 1), pred_rank=pr)
+
+    def sample_forward(self, x_prev: torch.Tensor, q: torch.Tensor, e: Optional[torch.Tensor],
+                       idx, y, record: Optional[Record], pred_factor: torch.Tensor):
+        """Forward step of the path sampler: returns (x_k, w_obs_k) for the ns paths in the
+        columns of x_prev (n x ns); q (n x ns) and e (m x ns) are the step's draws."""
+        ns = x_prev.shape[1]
+        m = 0 if idx is None else int(idx.numel())
+        inp = self._sample_input(idx, y, record, pred_factor)
+        x = torch.empty_like(x_prev)
+        w = torch.empty((max(m, 1), ns), dtype=torch.float32, device="cuda")
+        L.cakf_sample_forward(self.ctx, ns, x_prev.contiguous(), q.contiguous(),
+                              e.contiguous() if m else None, inp, x, w if m else None)
+        return x, w[:m]
+
+    def sample_lift(self, idx, w_obs: torch.Tensor, ns: int) -> torch.Tensor:
+        m = 0 if idx is None else int(idx.numel())
+        out = torch.empty((self.n, ns), dtype=torch.float32, device="cuda")
+        L.cakf_sample_lift(self.ctx, ns, idx if m else None, w_obs.contiguous() if m else None,
+                           m, out)
+        return out
+
+    def sample_backward(self, x: torch.Tensor, factor: torch.Tensor, idx,
+                        record: Optional[Record], pred_factor: torch.Tensor,
+                        w_obs: Optional[torch.Tensor], ws_next: torch.Tensor):
+        """Backward step of the path sampler: returns (xs_k, ws_k)."""
+        ns = x.shape[1]
+        factor = factor.contiguous()
+        m = 0 if idx is None else int(idx.numel())
+        inp = self._sample_input(idx, None, record, pred_factor)
+        xs = torch.empty_like(x)
+        ws = torch.empty_like(ws_next)
+        L.cakf_sample_backward(self.ctx, ns, x.contiguous(), factor if factor.shape[1] else None,
+                               max(factor.shape[1], 1), factor.shape[1], inp,
+                               w_obs.contiguous() if m else None, ws_next.contiguous(), xs, ws)
+        return xs, ws
 
     def loglik_grad(self, tape) -> list:
         """d loglik / d(lengthscale, ou_coeff, signal_var, noise_var) over a recorded run

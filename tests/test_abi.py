@@ -44,7 +44,8 @@ def test_binding_structs_follow_the_header():
     from paper_2405_08971_amd import _lib
     for cname, pyname in [("cakf_config", _lib.cakf_config), ("cakf_record", _lib.cakf_record),
                           ("cakf_smooth_input", _lib.cakf_smooth_input),
-                          ("cakf_tape_step", _lib.cakf_tape_step)]:
+                          ("cakf_tape_step", _lib.cakf_tape_step),
+                          ("cakf_sample_input", _lib.cakf_sample_input)]:
         assert [f[0] for f in pyname._fields_] == header_struct_fields(cname), cname
 
 
