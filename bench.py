@@ -35,6 +35,8 @@ PEAK_HBM = 8.0e12                      # B / s
 
 
 BLOCK_SIZES = (8, 32)      # actions per round of the block-residual policy timings
+SAMPLE_PATHS = 32          # paths per call of the path-sampler timing
+SAMPLE_STEPS = 20          # steps of the path-sampler timing
 
 
 def parse():
@@ -175,7 +177,9 @@ def next_rows(seed=0):
         n = 16384 differentiation workload (Matern-3/2, m = 4096, i = 64, r = 256, FP32),
         over T = 50 steps: the forward pass with its tape, then the backward sweep;
       * the filter and the computation-aware RTS smoother (Alg. 3) on the n = 16384
-        great-circle workload (Matern-3/2, m = 4096, i = 64, r = 256), T = 100."""
+        great-circle workload (Matern-3/2, m = 4096, i = 64, r = 256), T = 100;
+      * the path sampler (App. C) on the same workload, SAMPLE_PATHS paths over the first
+        SAMPLE_STEPS steps, forward and backward."""
     import torch
     from paper_2405_08971_amd.autograd import loglik
     from paper_2405_08971_amd.filter import CAKF, Record
@@ -241,6 +245,64 @@ def next_rows(seed=0):
         "smoother_ms_per_step": (t2 - t1) * 1e3 / (cfg.T - 1),
         "note": "filter steps include copying M_k and M_k^- out for the smoother"}
     del fwd
+    torch.cuda.empty_cache()
+
+    # path sampler (App. C) on the same workload: SAMPLE_PATHS joint paths, forward and
+    # backward, over the first SAMPLE_STEPS steps.  Prior and process-noise draws come
+    # from the random-Fourier-feature surrogate of the prior (generated on the device
+    # with torch before the timed regions).
+    T = SAMPLE_STEPS
+    ns = SAMPLE_PATHS
+    f = CAKF(X, nu2=cfg.nu2, dist="geodesic", lengthscale=cfg.ell, signal_var=cfg.sigma_f2,
+             noise_var=cfg.noise_var, ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i,
+             max_rank=cfg.r, policy="cg", prec="bf16x3", sample_paths=ns)
+    fwd = []
+    for idx, y in steps[:T]:
+        f.predict()
+        _, Mp = f.state()
+        rec = Record(cfg.m, cfg.i)
+        f.update(idx, y, None, rec)
+        _, M = f.state()
+        fwd.append((Mp, M, idx, y, rec))
+        f.truncate()
+    omega, phase, scale = wl.feature_map()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed + 71)
+    Om = torch.from_numpy(omega.astype(np.float32)).cuda()
+    Ph = torch.from_numpy(phase.astype(np.float32)).cuda()
+    feats = scale * torch.cos(X @ Om.T + Ph)
+    J = Om.shape[0]
+    x0 = feats @ torch.randn((J, ns), generator=gen, device="cuda")
+    qs = [math.sqrt(1.0 - cfg.a ** 2) * (feats @ torch.randn((J, ns), generator=gen,
+                                                             device="cuda"))
+          for _ in range(T)]
+    es = [torch.randn((cfg.m, ns), generator=gen, device="cuda") for _ in range(T)]
+    del feats
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = x0
+    xs_f, w_f = [], []
+    for k in range(T):
+        Mp, M, idx, y, rec = fwd[k]
+        x, w = f.sample_forward(x, qs[k], es[k], idx, y, rec, Mp)
+        xs_f.append(x)
+        w_f.append(w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ws = f.sample_lift(fwd[T - 1][2], w_f[T - 1], ns)
+    for k in range(T - 2, -1, -1):
+        Mp, M, idx, y, rec = fwd[k]
+        _, ws = f.sample_backward(xs_f[k], M, idx, rec, Mp, w_f[k], ws)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f.close()
+    out["sampler"] = {
+        "workload": f"{cfg.name}: n={cfg.n} sphere, Matern-{cfg.nu2}/2 great-circle, m={cfg.m}, "
+                    f"i={cfg.i} CG actions, r={cfg.r}, {ns} paths, T={T}, bf16x3 products",
+        "forward_ms_per_step": (t1 - t0) * 1e3 / T,
+        "backward_ms_per_step": (t2 - t1) * 1e3 / (T - 1),
+        "note": "prior draws from the random-Fourier-feature surrogate (2048 features)"}
+    del fwd, xs_f, w_f, qs, es
     torch.cuda.empty_cache()
     return out
 

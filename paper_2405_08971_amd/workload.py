@@ -167,6 +167,14 @@ class Workload:
         feats = np.cos(Xs @ self._omega.T + self._phase)
         return math.sqrt(self.cfg.sigma_f2 * 2.0 / self.n_features) * (feats @ w)
 
+    def feature_map(self):
+        """(omega, phase, scale) of the random-Fourier-feature surrogate of the spatial
+        prior: phi(x) = scale * cos(omega x + phase), so that phi(x)^T w with w ~ N(0, I)
+        is an approximate draw from N(0, Sigma)."""
+        if not self._prior_ready:
+            self._init_prior()
+        return self._omega, self._phase, math.sqrt(self.cfg.sigma_f2 * 2.0 / self.n_features)
+
     def obs_indices(self, k: int) -> np.ndarray:
         """m distinct observed indices at step k >= 1 (int64, unsorted)."""
         rng = np.random.default_rng(np.random.SeedSequence([self.seed, 23, k, self.cfg.n]))
