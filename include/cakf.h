@@ -226,6 +226,24 @@ int cakf_smooth_begin(cakf_ctx* ctx, const int32_t* idx, const float* w_obs,
 int cakf_smooth_step(cakf_ctx* ctx, const cakf_smooth_input* in, float* mean_out,
                      float* factor_out, int ld_out, float* var_out, int* out_rank);
 
+/* Temporal interpolation (App. C, the corollary on temporal interpolation): the
+ * filter's or the smoother's moments at a time t with t_k <= t < t_{k+1}, from step k's
+ * filter moments (in->mean = m_k, in->factor = M_k untruncated; the other fields are not
+ * read) and, smoothed != 0, the smoother's current messages ws_{k+1}, Ws_{k+1}:
+ *   filter    m(t)  = A(t, t_k) m_k,     M(t) = A(t, t_k) M_k,  P(t) = Sigma - M(t) M(t)^T
+ *   smoother  ms(t) = m(t) + P(t) A(t_{k+1}, t) ws_{k+1},
+ *             Ms(t) = [M(t) | P(t) A(t_{k+1}, t) Ws_{k+1}]
+ * a_left = A(t, t_k), a_right = A(t_{k+1}, t), both in (0, 1]; for the OU prior
+ * a_left = exp(-(t - t_k) / ell_t) and a_right = exp(-(t_{k+1} - t) / ell_t).  The
+ * messages of step k+1 are current between cakf_smooth_step for step k+1 (or
+ * cakf_smooth_begin when k + 1 = T) and cakf_smooth_step for step k; interpolation does
+ * not advance them.  Before the first step pass m = 0 and rank 0 (the prior); after the
+ * last step the smoothed moments are the filter's (smoothed = 0).  Outputs as in
+ * cakf_smooth_step; *out_rank = rank (+ the messages' rank when smoothed). */
+int cakf_interpolate(cakf_ctx* ctx, const cakf_smooth_input* in, double a_left,
+                     double a_right, int smoothed, float* mean_out, float* factor_out,
+                     int ld_out, float* var_out, int* out_rank);
+
 /* ------------------------------------------------------------ path sampler (App. C)
  * Joint sample paths of the computation-aware filter and smoother (the CAKF/CAKS
  * sampler): draws from the prior are pushed through the gains of a recorded filter run,

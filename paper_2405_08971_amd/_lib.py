@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
             "cakf_smooth_begin": (i, [vp, vp, vp, vp, i]),
             "cakf_smooth_step": (i, [vp, ctypes.POINTER(cakf_smooth_input), vp, vp, i, vp,
                                      ctypes.POINTER(i)]),
+            "cakf_interpolate": (i, [vp, ctypes.POINTER(cakf_smooth_input), d, d, i, vp, vp,
+                                     i, vp, ctypes.POINTER(i)]),
             "cakf_sample_forward": (i, [vp, i, vp, vp, vp, ctypes.POINTER(cakf_sample_input),
                                         vp, vp]),
             "cakf_sample_lift": (i, [vp, i, vp, vp, i, vp]),
@@ -263,3 +265,13 @@ def cakf_sample_backward(ctx: int, ns: int, x, factor, ld: int, rank: int,
     check(lib().cakf_sample_backward(ctx, ns, ptr(x), ptr(factor), ld, rank, ctypes.byref(inp),
                                      ptr(w_obs), ptr(ws_next), ptr(xs_out), ptr(ws_out)),
           "cakf_sample_backward")
+
+
+def cakf_interpolate(ctx: int, inp: cakf_smooth_input, a_left: float, a_right: float,
+                     smoothed: bool, mean_out=None, factor_out=None, ld_out: int = 0,
+                     var_out=None) -> int:
+    rank = ctypes.c_int()
+    check(lib().cakf_interpolate(ctx, ctypes.byref(inp), a_left, a_right, 1 if smoothed else 0,
+                                 ptr(mean_out), ptr(factor_out), ld_out, ptr(var_out),
+                                 ctypes.byref(rank)), "cakf_interpolate")
+    return rank.value

@@ -881,25 +881,31 @@ extern "C" int cakf_smooth_begin(cakf_ctx* c, const int32_t* idx, const float* w
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 
-extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float* mean_out,
-                                float* factor_out, int ld_out, float* var_out, int* out_rank) {
-    if (!c || !in || !c->sm_started || !in->mean) return CAKF_E_ARG;
+static int smooth_input_ok(const cakf_ctx* c, const cakf_smooth_input* in) {
+    if (!in || !in->mean) return 0;
     if (in->rank < 0 || in->rank > c->Kmax || (in->rank > 0 && (!in->factor || in->ld < in->rank)))
-        return CAKF_E_ARG;
+        return 0;
     if (in->pred_rank < 0 || in->pred_rank > c->Kmax ||
         (in->pred_rank > 0 && (!in->pred_factor || in->pred_ld < in->pred_rank)))
-        return CAKF_E_ARG;
+        return 0;
     if (in->m < 0 || in->m > c->mmax || (in->m > 0 && (!in->idx || !in->w_obs || !in->W_obs)))
-        return CAKF_E_ARG;
+        return 0;
+    return 1;
+}
+
+// Smoothed moments from the filter moments (mean, factor) scaled by g and the current
+// messages [ws Ws] propagated by ar:  Bs = ar [ws Ws],  Y = Sigma Bs,
+// Z = Y - g^2 M (M^T Bs),  mean_out = g m + Z[:, 0],  factor_out = [g M | Z[:, 1:]].
+// Leaves Bs in sm_B and Y in sm_Y.
+static int smooth_moments(cakf_ctx* c, const cakf_smooth_input* in, float g, float ar,
+                          float* mean_out, float* factor_out, int ld_out, float* var_out) {
     const int rs = c->sm_rank;
     const int b = 1 + rs;
-    if (factor_out && ld_out < in->rank + rs) return CAKF_E_ARG;
     hipStream_t st = c->stream;
-    const float a = (float)c->cfg.ou_coeff;
-    const float one = 1.0f, zero = 0.0f, mone = -1.0f;
+    const float one = 1.0f, zero = 0.0f, mg2 = -g * g;
     float* Ws = c->sm_W[c->sm_cur];
-    // Bs = A^T [ws Ws]
-    launch_smooth_pack(c->sm_ws, Ws, c->ldWs, c->n, c->np, rs, a, c->sm_B, c->bps, st);
+    // Bs = ar [ws Ws]
+    launch_smooth_pack(c->sm_ws, Ws, c->ldWs, c->n, c->np, rs, ar, c->sm_B, c->bps, st);
     // Y = Sigma Bs (kernel matrix over all points, never stored)
     {
         PhaseTimer t(c, CAKF_PHASE_BLOCK_PRODUCT);
@@ -908,7 +914,7 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
                              (float)c->cfg.signal_var, c->sm_Y, c->bps, st,
                              block_product_splits(c->n, c->np, b, c->bpart_elems), c->bpart);
     }
-    // Z = P_k A^T [ws Ws] = Y - M_k (M_k^T Bs)
+    // Z = Y - g^2 M (M^T Bs)
     HIP_TRY(hipMemcpyAsync(c->sm_Z, c->sm_Y, (size_t)c->n * c->bps * sizeof(float),
                            hipMemcpyDeviceToDevice, st));
     if (in->rank > 0) {
@@ -916,11 +922,26 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
                                in->rank, b, c->n, &one, in->factor, in->ld, c->sm_B, c->bps, &zero,
                                c->sm_Q, c->Kmax));
         BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, b,
-                               c->n, in->rank, &mone, c->sm_Q, c->Kmax, in->factor, in->ld, &one,
+                               c->n, in->rank, &mg2, c->sm_Q, c->Kmax, in->factor, in->ld, &one,
                                c->sm_Z, c->bps));
     }
-    launch_smooth_out(in->mean, in->factor, in->ld, in->rank, c->sm_Z, c->bps, b, c->n,
+    launch_smooth_out(in->mean, in->factor, in->ld, in->rank, g, c->sm_Z, c->bps, b, c->n,
                       (float)c->cfg.signal_var, mean_out, factor_out, ld_out, var_out, st);
+    return CAKF_OK;
+}
+
+extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float* mean_out,
+                                float* factor_out, int ld_out, float* var_out, int* out_rank) {
+    if (!c || !c->sm_started || !smooth_input_ok(c, in)) return CAKF_E_ARG;
+    const int rs = c->sm_rank;
+    const int b = 1 + rs;
+    if (factor_out && ld_out < in->rank + rs) return CAKF_E_ARG;
+    hipStream_t st = c->stream;
+    const float one = 1.0f, zero = 0.0f, mone = -1.0f;
+    float* Ws = c->sm_W[c->sm_cur];
+    int rc = smooth_moments(c, in, 1.0f, (float)c->cfg.ou_coeff, mean_out, factor_out, ld_out,
+                            var_out);
+    if (rc) return rc;
     if (out_rank) *out_rank = in->rank + rs;
     // Pm = P_k^- A^T [ws Ws] = Y - M_k^- (M_k^-^T Bs), reusing Z
     const int i = in->m > 0 ? c->imax : 0;
@@ -958,6 +979,27 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
         c->sm_cur = 1 - c->sm_cur;
         c->sm_rank = K;
     }
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+extern "C" int cakf_interpolate(cakf_ctx* c, const cakf_smooth_input* in, double a_left,
+                                double a_right, int smoothed, float* mean_out,
+                                float* factor_out, int ld_out, float* var_out, int* out_rank) {
+    if (!c || !smooth_input_ok(c, in)) return CAKF_E_ARG;
+    if (!(a_left > 0.0) || a_left > 1.0 || !(a_right > 0.0) || a_right > 1.0) return CAKF_E_ARG;
+    if (smoothed && (!c->sm_started || !c->Xp)) return CAKF_E_ARG;
+    const int rs = smoothed ? c->sm_rank : 0;
+    if (factor_out && ld_out < in->rank + rs) return CAKF_E_ARG;
+    const float g = (float)a_left;
+    if (smoothed) {
+        int rc = smooth_moments(c, in, g, (float)a_right, mean_out, factor_out, ld_out, var_out);
+        if (rc) return rc;
+    } else {
+        launch_smooth_out(in->mean, in->factor, in->ld, in->rank, g, nullptr, 0, 1, c->n,
+                          (float)c->cfg.signal_var, mean_out, factor_out, ld_out, var_out,
+                          c->stream);
+    }
+    if (out_rank) *out_rank = in->rank + rs;
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 

@@ -115,8 +115,8 @@ void launch_pick_rotation(const double* E, int K, int r, float* Vr, double* rot_
 // ---- smooth.hip
 void launch_smooth_pack(const float* ws, const float* Ws, int ldw, int n, int np, int rs,
                         float a, float* Bs, int ldb, hipStream_t st);
-void launch_smooth_out(const float* mean, const float* M, int ldm, int rank, const float* Z,
-                       int ldz, int b, int n, float sigma_f2, float* mean_out,
+void launch_smooth_out(const float* mean, const float* M, int ldm, int rank, float g,
+                       const float* Z, int ldz, int b, int n, float sigma_f2, float* mean_out,
                        float* factor_out, int ldo, float* var_out, hipStream_t st);
 void launch_gather_rows(const float* A, int lda, const int32_t* idx, int m, int n, int cols,
                         float* out, int ldo, hipStream_t st);

@@ -30,12 +30,15 @@ void launch_smooth_pack(const float* ws, const float* Ws, int ldw, int n, int np
                        dim3(256), 0, st, ws, Ws, ldw, n, np, rs, a, Bs, ldb);
 }
 
-// Smoothed moments of step k from Z = P_k A^T [ws Ws] (n x b, ld ldz):
-//   mean_out = m_k + Z[:, 0];  factor_out = [M_k | Z[:, 1:b]];
-//   var_out = sigma_f2 - |M_k[p, :]|^2 - |Z[p, 1:b]|^2   (FP64 accumulation).
+// Smoothed moments of step k from Z = P_k A^T [ws Ws] (n x b, ld ldz), with the filter
+// moments scaled by g (1 at a step; A(t, t_k) at an interpolated time t):
+//   mean_out = g m_k + Z[:, 0];  factor_out = [g M_k | Z[:, 1:b]];
+//   var_out = sigma_f2 - |g M_k[p, :]|^2 - |Z[p, 1:b]|^2   (FP64 accumulation).
+// Z == nullptr: the filter moments alone (b ignored).
 __global__ __launch_bounds__(256) void k_smooth_out(const float* __restrict__ mean,
                                                     const float* __restrict__ M, int ldm,
-                                                    int rank, const float* __restrict__ Z,
+                                                    int rank, float g,
+                                                    const float* __restrict__ Z,
                                                     int ldz, int b, int n, float sigma_f2,
                                                     float* __restrict__ mean_out,
                                                     float* __restrict__ factor_out, int ldo,
@@ -44,30 +47,32 @@ __global__ __launch_bounds__(256) void k_smooth_out(const float* __restrict__ me
     const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= n) return;
     const float* Mr = M + (size_t)p * ldm;
-    const float* Zr = Z + (size_t)p * ldz;
+    const float* Zr = Z ? Z + (size_t)p * ldz : nullptr;
     double s = 0.0;
     for (int c = lane; c < rank; c += 64) {
-        const float v = Mr[c];
+        const float v = g * Mr[c];
         s = __builtin_fma((double)v, (double)v, s);
         if (factor_out) factor_out[(size_t)p * ldo + c] = v;
     }
-    for (int c = 1 + lane; c < b; c += 64) {
-        const float v = Zr[c];
-        s = __builtin_fma((double)v, (double)v, s);
-        if (factor_out) factor_out[(size_t)p * ldo + rank + c - 1] = v;
+    if (Zr) {
+        for (int c = 1 + lane; c < b; c += 64) {
+            const float v = Zr[c];
+            s = __builtin_fma((double)v, (double)v, s);
+            if (factor_out) factor_out[(size_t)p * ldo + rank + c - 1] = v;
+        }
     }
     s = wave_sum(s);
     if (lane == 0) {
-        if (mean_out) mean_out[p] = mean[p] + Zr[0];
+        if (mean_out) mean_out[p] = g * mean[p] + (Zr ? Zr[0] : 0.0f);
         if (var_out) var_out[p] = (float)((double)sigma_f2 - s);
     }
 }
 
-void launch_smooth_out(const float* mean, const float* M, int ldm, int rank, const float* Z,
-                       int ldz, int b, int n, float sigma_f2, float* mean_out,
+void launch_smooth_out(const float* mean, const float* M, int ldm, int rank, float g,
+                       const float* Z, int ldz, int b, int n, float sigma_f2, float* mean_out,
                        float* factor_out, int ldo, float* var_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_smooth_out, dim3((n + 3) / 4), dim3(256), 0, st, mean, M, ldm, rank, Z,
-                       ldz, b, n, sigma_f2, mean_out, factor_out, ldo, var_out);
+    hipLaunchKernelGGL(k_smooth_out, dim3((n + 3) / 4), dim3(256), 0, st, mean, M, ldm, rank, g,
+                       Z, ldz, b, n, sigma_f2, mean_out, factor_out, ldo, var_out);
 }
 
 // Gather rows of a row-major matrix: out[q, 0:cols] = A[idx[q], 0:cols].

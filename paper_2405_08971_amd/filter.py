@@ -205,6 +205,27 @@ class CAKF:
                                w_obs.contiguous() if m else None, ws_next.contiguous(), xs, ws)
         return xs, ws
 
+    def interpolate(self, mean, factor, a_left: float, a_right: float = 1.0,
+                    smoothed: bool = False, want_factor: bool = False):
+        """Moments at a time between steps k and k+1 from step k's filter moments (mean,
+        untruncated factor) and, smoothed, the smoother's current messages (those of
+        step k+1).  Returns (mean, marginal variances, factor or None)."""
+        factor = factor.contiguous()
+        rank = factor.shape[1]
+        inp = L.cakf_smooth_input(
+            mean=L.ptr(mean), factor=L.ptr(factor) if rank else None, ld=max(rank, 1),
+            rank=rank, pred_factor=None, pred_ld=1, pred_rank=0, idx=None, w_obs=None,
+            W_obs=None, m=0)
+        out_mean = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        out_var = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        out_fac, ld = None, 0
+        if want_factor:
+            ld = rank + self.max_rank + self.max_actions
+            out_fac = torch.empty((self.n, ld), dtype=torch.float32, device="cuda")
+        r = L.cakf_interpolate(self.ctx, inp, a_left, a_right, smoothed, out_mean, out_fac, ld,
+                               out_var)
+        return out_mean, out_var, (out_fac[:, :r] if want_factor else None)
+
     def loglik_grad(self, tape) -> list:
         """d loglik / d(lengthscale, ou_coeff, signal_var, noise_var) over a recorded run
         (a sequence of cakf_tape_step; see paper_2405_08971_amd.autograd)."""
