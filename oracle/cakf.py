@@ -67,6 +67,10 @@ class Model:
     def n(self) -> int:
         return self.X.shape[0]
 
+    def transition(self, V: np.ndarray) -> np.ndarray:
+        """A V for the state transition of one step (OU: A = a I, Lemma C.1)."""
+        return self.a * V
+
     def cov_matmul(self, rows, cols, V) -> np.ndarray:
         """Sigma[rows, cols] @ V  (rows/cols are index arrays or None for all)."""
         A = self.X if rows is None else self.X[rows]
@@ -296,8 +300,8 @@ def run_filter(model: Model, steps, max_actions: int, r_cap: int, policy: str = 
     Mp = np.zeros((n, 0)) if M0 is None else np.asarray(M0, np.float64)
     recs = []
     for k, item in enumerate(steps, start=1):
-        m_pred = model.a * m
-        M_pred = model.a * Mp
+        m_pred = model.transition(m)
+        M_pred = model.transition(Mp)
         if item is None:
             m, M = m_pred, M_pred
             idx = S = w_obs = W_obs = None
