@@ -80,8 +80,23 @@ typedef struct cakf_ctx cakf_ctx;
 #define CAKF_POLICY_GIVEN 1
 #define CAKF_POLICY_BLOCK 2
 
+/* Temporal factor of the separable prior (Lemma C.1):
+ *   OU        - exponential (Matérn-1/2) kernel exp(-|t - t'| / ell_t): the state is the
+ *               value at the n points, A = a I with a = exp(-dt / ell_t) (ou_coeff);
+ *   MATERN32  - Matérn-3/2 kernel (1 + lam |tau|) exp(-lam |tau|), lam = sqrt(3) / ell_t:
+ *               the state stacks the values (rows 0..n-1) and the time derivatives
+ *               scaled by 1/lam (rows n..2n-1), so that its stationary covariance is
+ *               I_2 (x) Sigma; with s = lam dt and a = exp(-s) (ou_coeff) one step is
+ *               A = a [[1 + s, s], [-s, 1 - s]] (x) I_n.  Observations pick value rows.
+ * The state (mean, factor) has n rows (OU) or 2n rows (MATERN32).  MATERN32 supports
+ * predict, update (any policy), truncate, step, the state and marginal-variance calls
+ * (value rows) and the log-likelihood; the smoother, sampler and derivative workspaces
+ * are OU-only (cakf_create returns CAKF_E_ARG). */
+#define CAKF_TEMPORAL_OU       0
+#define CAKF_TEMPORAL_MATERN32 1
+
 typedef struct {
-    int n;                  /* spatial points = state dimension, >= 1                */
+    int n;                  /* spatial points (state dimension n, or 2n), >= 1       */
     int dim;                /* coordinates per point: 2 or 3                         */
     const float* X;         /* device, n x dim row-major; read once in cakf_create   */
     int kernel;             /* CAKF_MATERN12/32/52                                   */
@@ -89,7 +104,9 @@ typedef struct {
     double lengthscale;     /* spatial lengthscale ell > 0                           */
     double signal_var;      /* sigma_f^2 > 0                                         */
     double noise_var;       /* observation noise variance > 0                        */
-    double ou_coeff;        /* a = exp(-dt / ell_t), 0 < a <= 1                      */
+    double ou_coeff;        /* a = exp(-dt / ell_t) (OU) or exp(-sqrt(3) dt / ell_t)
+                               (MATERN32), 0 < a <= 1                                */
+    int temporal;           /* CAKF_TEMPORAL_*                                        */
     int max_obs;            /* largest m passed to cakf_update                       */
     int max_actions;        /* action budget i per update, 1..256 (at most m used)   */
     int max_rank;           /* rank cap r of the truncated factor, 1..1024           */
@@ -134,17 +151,18 @@ void cakf_destroy(cakf_ctx* ctx);
 /* Reset the filter state to the prior (mean 0, empty factor). */
 int cakf_reset(cakf_ctx* ctx);
 
-/* Device views of the context-owned filter state: mean (n), factor (n x rank,
- * row-major with leading dimension *ld).  The pointers stay valid until the next
+/* Device views of the context-owned filter state: mean (N), factor (N x rank,
+ * row-major with leading dimension *ld); N = n, or 2n with the Matérn-3/2 temporal
+ * factor.  The pointers stay valid until the next
  * cakf_update / cakf_truncate / cakf_step / cakf_set_state / cakf_destroy.  Any output
  * pointer may be NULL. */
 int cakf_state(cakf_ctx* ctx, float** mean, float** factor, int* ld, int* rank);
 
-/* Copy the state out into caller-owned device buffers: mean (n) and factor (n x rank,
+/* Copy the state out into caller-owned device buffers: mean (N) and factor (N x rank,
  * leading dimension ld >= rank).  Either pointer may be NULL. */
 int cakf_copy_state(cakf_ctx* ctx, float* mean, float* factor, int ld);
 
-/* Copy a state in (device buffers: mean n, factor n x rank with leading dimension ld).
+/* Copy a state in (device buffers: mean N, factor N x rank with leading dimension ld).
  * rank <= max_rank. */
 int cakf_set_state(cakf_ctx* ctx, const float* mean, const float* factor, int ld, int rank);
 
@@ -171,8 +189,8 @@ int cakf_step(cakf_ctx* ctx, const int32_t* idx, const float* y, int m,
               const float* actions, const cakf_record* rec);
 
 /* Marginal variances diag(Sigma - M M^T) of the current state at the state indices
- * rows (device int32, count entries; NULL = all n) into out (device, count).  A row
- * index outside [0, n) yields NaN. */
+ * rows (device int32, count entries; NULL = all n) into out (device, count): the values
+ * at the points (rows < n).  A row index outside [0, n) yields NaN. */
 int cakf_marginal_var(cakf_ctx* ctx, const int32_t* rows, int count, float* out);
 
 /* Log marginal likelihood of the data seen since the last reset, as the filter defines

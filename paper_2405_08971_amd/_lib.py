@@ -18,6 +18,7 @@ CAKF_OK, CAKF_E_ARG, CAKF_E_HIP, CAKF_E_NOMEM, CAKF_E_STATE, CAKF_E_SOLVER = 0, 
 MATERN = {1: 1, 3: 3, 5: 5}
 DIST = {"euclid": 0, "geodesic": 1}
 PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+TEMPORAL = {"ou": 0, "matern32": 1}
 POLICY = {"cg": 0, "given": 1, "block": 2}
 PHASES = ("sym_tiles", "form_u", "tail", "next_action", "block_product", "gram", "eig",
           "rotate", "predict", "update", "truncate")
@@ -32,6 +33,7 @@ class cakf_config(ctypes.Structure):
         ("kernel", ctypes.c_int), ("dist", ctypes.c_int),
         ("lengthscale", ctypes.c_double), ("signal_var", ctypes.c_double),
         ("noise_var", ctypes.c_double), ("ou_coeff", ctypes.c_double),
+        ("temporal", ctypes.c_int),
         ("max_obs", ctypes.c_int), ("max_actions", ctypes.c_int), ("max_rank", ctypes.c_int),
         ("policy", ctypes.c_int), ("block_actions", ctypes.c_int),
         ("resid_tol", ctypes.c_double),

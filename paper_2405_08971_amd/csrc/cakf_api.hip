@@ -113,6 +113,7 @@ struct cakf_ctx {
     float *sp_B, *sp_W, *sp_Y, *sp_D, *sp_D2, *sp_R, *sp_Z, *sp_Q;
     __bf16 *sp_Bth, *sp_Btl;
     float4* sp_Xo;
+    int N;            // state rows: n, or 2n with the Matérn-3/2 temporal factor
     // partial products of block products split along the observation axis
     float* bpart;
     size_t bpart_elems;
@@ -214,6 +215,11 @@ static int validate(const cakf_config* c) {
     if (c->smoother && (size_t)c->n * (c->max_rank + 1) > ((size_t)1 << 31)) return CAKF_E_ARG;
     if (c->gradient && c->max_actions > 159) return CAKF_E_ARG;
     if (c->sample_paths < 0 || c->sample_paths > 256) return CAKF_E_ARG;
+    if (c->temporal != CAKF_TEMPORAL_OU && c->temporal != CAKF_TEMPORAL_MATERN32)
+        return CAKF_E_ARG;
+    if (c->temporal == CAKF_TEMPORAL_MATERN32 &&
+        (c->smoother || c->gradient || c->sample_paths > 0))
+        return CAKF_E_ARG;
     return CAKF_OK;
 }
 
@@ -232,6 +238,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         return CAKF_E_HIP;
     }
     c->n = cfg->n;
+    c->N = cfg->temporal == CAKF_TEMPORAL_MATERN32 ? 2 * cfg->n : cfg->n;
     c->r = cfg->max_rank;
     c->imax = cfg->max_actions;
     c->mmax = cfg->max_obs;
@@ -247,9 +254,9 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     // largest block count of a next_action launch (the column-product and Mo^T s partials)
     const int nablk = std::max(next_action_blocks(c->mmax, 4, 4), next_action_blocks(c->mmax, 16, 1));
     rc = CAKF_OK;
-    rc |= dalloc(&c->mean, n);
-    rc |= dalloc(&c->M[0], n * c->ldM);
-    rc |= dalloc(&c->M[1], n * c->ldM);
+    rc |= dalloc(&c->mean, (size_t)c->N);
+    rc |= dalloc(&c->M[0], (size_t)c->N * c->ldM);
+    rc |= dalloc(&c->M[1], (size_t)c->N * c->ldM);
     rc |= dalloc(&c->Xs, n);
     rc |= dalloc(&c->Xo, c->mpmax);
     rc |= dalloc(&c->r0, c->mpmax);
@@ -418,7 +425,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     const double scale = 1.4426950408889634 * std::sqrt((double)nu2) / cfg->lengthscale;
     launch_prescale(cfg->X, c->n, cfg->dim, (float)scale, cfg->dist, c->Xs, c->stream);
     if (c->Xp) launch_pad_points(c->Xs, c->n, c->np, c->Xp, c->stream);
-    if (hipMemsetAsync(c->mean, 0, n * sizeof(float), c->stream) != hipSuccess ||
+    if (hipMemsetAsync(c->mean, 0, (size_t)c->N * sizeof(float), c->stream) != hipSuccess ||
         hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         rocblas_destroy_handle(c->blas);
@@ -443,7 +450,7 @@ extern "C" void cakf_destroy(cakf_ctx* c) {
 
 extern "C" int cakf_reset(cakf_ctx* c) {
     if (!c) return CAKF_E_ARG;
-    HIP_TRY(hipMemsetAsync(c->mean, 0, (size_t)c->n * sizeof(float), c->stream));
+    HIP_TRY(hipMemsetAsync(c->mean, 0, (size_t)c->N * sizeof(float), c->stream));
     HIP_TRY(hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream));
     c->rank = 0;
     return CAKF_OK;
@@ -461,10 +468,10 @@ extern "C" int cakf_state(cakf_ctx* c, float** mean, float** factor, int* ld, in
 extern "C" int cakf_copy_state(cakf_ctx* c, float* mean, float* factor, int ld) {
     if (!c || (factor && ld < c->rank)) return CAKF_E_ARG;
     if (mean)
-        HIP_TRY(hipMemcpyAsync(mean, c->mean, (size_t)c->n * sizeof(float),
+        HIP_TRY(hipMemcpyAsync(mean, c->mean, (size_t)c->N * sizeof(float),
                                hipMemcpyDeviceToDevice, c->stream));
     if (factor && c->rank > 0)
-        launch_copy_rows(c->M[c->cur], c->ldM, factor, ld, c->n, c->rank, c->stream);
+        launch_copy_rows(c->M[c->cur], c->ldM, factor, ld, c->N, c->rank, c->stream);
     return CAKF_OK;
 }
 
@@ -472,9 +479,9 @@ extern "C" int cakf_set_state(cakf_ctx* c, const float* mean, const float* facto
                               int rank) {
     if (!c || !mean || rank < 0 || rank > c->r || (rank > 0 && (!factor || ld < rank)))
         return CAKF_E_ARG;
-    HIP_TRY(hipMemcpyAsync(c->mean, mean, (size_t)c->n * sizeof(float), hipMemcpyDeviceToDevice,
+    HIP_TRY(hipMemcpyAsync(c->mean, mean, (size_t)c->N * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
-    if (rank > 0) launch_copy_rows(factor, ld, c->M[c->cur], c->ldM, c->n, rank, c->stream);
+    if (rank > 0) launch_copy_rows(factor, ld, c->M[c->cur], c->ldM, c->N, rank, c->stream);
     c->rank = rank;
     return CAKF_OK;
 }
@@ -482,7 +489,15 @@ extern "C" int cakf_set_state(cakf_ctx* c, const float* mean, const float* facto
 extern "C" int cakf_predict(cakf_ctx* c) {
     if (!c) return CAKF_E_ARG;
     const float a = (float)c->cfg.ou_coeff;
-    if (a != 1.0f) launch_scale_state(c->mean, c->M[c->cur], c->n, c->ldM, c->rank, a, c->stream);
+    if (c->cfg.temporal == CAKF_TEMPORAL_MATERN32) {
+        // A^t = a [[1 + s, s], [-s, 1 - s]], s = -log a, on each point's (value, derivative)
+        const double ad = c->cfg.ou_coeff, sd = -std::log(ad);
+        const float t[4] = {(float)(ad * (1.0 + sd)), (float)(ad * sd), (float)(-ad * sd),
+                            (float)(ad * (1.0 - sd))};
+        launch_predict_pairs(c->mean, c->M[c->cur], c->n, c->ldM, c->rank, t, c->stream);
+    } else if (a != 1.0f) {
+        launch_scale_state(c->mean, c->M[c->cur], c->n, c->ldM, c->rank, a, c->stream);
+    }
     return CAKF_OK;
 }
 
@@ -669,14 +684,16 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
                              c->Bth, c->Btl, (float)c->cfg.signal_var, M + d.rank, c->ldM, st,
                              block_product_splits(c->n, d.mp, b, c->bpart_elems), c->bpart);
     }
+    // the scaled-derivative rows of Sigma_inf H^T [W w] are zero (I_2 (x) Sigma)
+    if (c->N > c->n) launch_zero_cols(M + (size_t)c->n * c->ldM + d.rank, c->ldM, c->N - c->n, b, st);
     if (d.rank > 0) {
         const float mone = -1.0f, one = 1.0f;
         // Y -= M^- Q  (the low-rank part of P^- H^T [W w])
         BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, b,
-                               c->n, d.rank, &mone, c->Q, c->r, M, c->ldM, &one, M + d.rank,
+                               c->N, d.rank, &mone, c->Q, c->r, M, c->ldM, &one, M + d.rank,
                                c->ldM));
     }
-    launch_mean_add(c->mean, M, c->n, c->ldM, d.rank + c->imax, st);
+    launch_mean_add(c->mean, M, c->N, c->ldM, d.rank + c->imax, st);
     launch_finish_record(c->ls, c->L, c->Linv, c->imax, rec->chol, rec->chol_inv, rec->loglik,
                          rec->n_actions, st);
     hipLaunchKernelGGL(k_count_diag, dim3(1), dim3(1), 0, st, c->ls, c->diag);
@@ -684,14 +701,14 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 
-// Replace the n x K factor M (row-major, ld) by M V_r in Mout (ld ldo), V_r the leading
+// Replace the rows x K factor M (row-major, ld) by M V_r in Mout (ld ldo), V_r the leading
 // r eigenvectors of M^T M (FP64 Gram, FP64 symmetric eigensolver, FP32 rotation).
-static int truncate_factor(cakf_ctx* c, const float* M, int ld, int K, int r, float* Mout,
-                           int ldo, double* rotation) {
+static int truncate_factor(cakf_ctx* c, const float* M, int rows, int ld, int K, int r,
+                           float* Mout, int ldo, double* rotation) {
     hipStream_t st = c->stream;
     {
         PhaseTimer t(c, CAKF_PHASE_GRAM);
-        launch_gram64(M, c->n, ld, K, c->G, c->gwork, c->gram_work_elems, st);
+        launch_gram64(M, rows, ld, K, c->G, c->gwork, c->gram_work_elems, st);
     }
     bool picked = false;
     {
@@ -721,7 +738,7 @@ static int truncate_factor(cakf_ctx* c, const float* M, int ld, int K, int r, fl
         const float one = 1.0f, zero = 0.0f;
         // Mout (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n)
         BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, r,
-                               c->n, K, &one, c->Vr, K, M, ld, &zero, Mout, ldo));
+                               rows, K, &one, c->Vr, K, M, ld, &zero, Mout, ldo));
     }
     return CAKF_OK;
 }
@@ -730,7 +747,7 @@ extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
     if (!c) return CAKF_E_ARG;
     const int K = c->rank;
     if (K <= c->r) return CAKF_OK;
-    int rc = truncate_factor(c, c->M[c->cur], c->ldM, K, c->r, c->M[1 - c->cur], c->ldM,
+    int rc = truncate_factor(c, c->M[c->cur], c->N, c->ldM, K, c->r, c->M[1 - c->cur], c->ldM,
                              rotation);
     if (rc) return rc;
     c->cur = 1 - c->cur;
@@ -972,7 +989,7 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
                            c->ldWs, st);
     const int K = i + rs;
     if (K > c->r) {
-        int rc = truncate_factor(c, Wn, c->ldWs, K, c->r, Ws, c->ldWs, nullptr);
+        int rc = truncate_factor(c, Wn, c->n, c->ldWs, K, c->r, Ws, c->ldWs, nullptr);
         if (rc) return rc;
         c->sm_rank = c->r;          // result landed in the current buffer
     } else {

@@ -32,6 +32,9 @@ void launch_prescale(const float* X, int n, int dim, float c, int dist, float4* 
                      hipStream_t st);
 void launch_scale_state(float* mean, float* M, int n, int ld, int rank, float a, hipStream_t st);
 void launch_mean_add(float* mean, const float* M, int n, int ld, int col, hipStream_t st);
+void launch_predict_pairs(float* mean, float* M, int n, int ld, int rank, const float t[4],
+                          hipStream_t st);
+void launch_zero_cols(float* M, int ld, int rows, int cols, hipStream_t st);
 void launch_marginal_var(const float* M, int n, int ld, int rank, float sigma_f2,
                          const int32_t* rows, int count, float* out, hipStream_t st);
 void launch_copy_rows(const float* src, int lds, float* dst, int ldd, int rows, int cols,

@@ -48,6 +48,46 @@ void launch_scale_state(float* mean, float* M, int n, int ld, int rank, float a,
     hipLaunchKernelGGL(k_scale_state, dim3(blocks), dim3(256), 0, st, mean, M, n, ld, rank, a);
 }
 
+// Predict of the Matérn-3/2 temporal state (value rows 0..n-1, scaled-derivative rows
+// n..2n-1): each point's pair of rows (p, n + p) of the mean and of the factor's first
+// rank columns is multiplied by the 2x2 transition [[t00, t01], [t10, t11]].
+__global__ void k_predict_pairs(float* __restrict__ mean, float* __restrict__ M, int n, int ld,
+                                int rank, float t00, float t01, float t10, float t11) {
+    const size_t total = (size_t)n * (rank + 1);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const size_t p = e / (rank + 1), c = e % (rank + 1);
+        float* v0 = c < (size_t)rank ? M + p * ld + c : mean + p;
+        float* v1 = c < (size_t)rank ? M + (p + n) * ld + c : mean + p + n;
+        const float a = *v0, b = *v1;
+        *v0 = __builtin_fmaf(t00, a, t01 * b);
+        *v1 = __builtin_fmaf(t10, a, t11 * b);
+    }
+}
+
+void launch_predict_pairs(float* mean, float* M, int n, int ld, int rank, const float t[4],
+                          hipStream_t st) {
+    const size_t total = (size_t)n * (rank + 1);
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_predict_pairs, dim3(blocks), dim3(256), 0, st, mean, M, n, ld, rank,
+                       t[0], t[1], t[2], t[3]);
+}
+
+// M[p, c0 + c] = 0 for p < rows, c < cols (the scaled-derivative rows of new columns).
+__global__ void k_zero_cols(float* __restrict__ M, int ld, int rows, int cols) {
+    const size_t total = (size_t)rows * cols;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x)
+        M[(e / cols) * ld + e % cols] = 0.0f;
+}
+
+void launch_zero_cols(float* M, int ld, int rows, int cols, hipStream_t st) {
+    const size_t total = (size_t)rows * cols;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_zero_cols, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
+                       dim3(256), 0, st, M, ld, rows, cols);
+}
+
 // m <- m + M[:, col]  (the mean column of the block product).
 __global__ void k_mean_add(float* __restrict__ mean, const float* __restrict__ M, int n, int ld,
                            int col) {

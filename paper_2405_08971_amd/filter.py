@@ -38,7 +38,8 @@ class CAKF:
 
     def __init__(self, X: torch.Tensor, *, nu2: int = 3, dist: str = "euclid",
                  lengthscale: float, signal_var: float = 1.0, noise_var: float,
-                 ou_coeff: float, max_obs: int, max_actions: int, max_rank: int,
+                 ou_coeff: float, temporal: str = "ou", max_obs: int, max_actions: int,
+                 max_rank: int,
                  policy: str = "cg", block_actions: int = 8, resid_tol: float = 0.0,
                  pivot_tol: float = 1e-10,
                  prec: str = "fp32", smoother: bool = False, gradient: bool = False,
@@ -47,13 +48,15 @@ class CAKF:
             raise ValueError("X must be a float32 (n, dim) device tensor")
         X = X.contiguous()
         self.n, self.dim = X.shape
+        self.N = self.n * (2 if temporal == "matern32" else 1)   # state rows
         self.max_actions, self.max_rank, self.max_obs = max_actions, max_rank, max_obs
         self.signal_var = signal_var
         self.policy = policy
         cfg = L.cakf_config(
             n=self.n, dim=self.dim, X=L.ptr(X), kernel=L.MATERN[nu2], dist=L.DIST[dist],
             lengthscale=lengthscale, signal_var=signal_var, noise_var=noise_var,
-            ou_coeff=ou_coeff, max_obs=max_obs, max_actions=max_actions, max_rank=max_rank,
+            ou_coeff=ou_coeff, temporal=L.TEMPORAL[temporal], max_obs=max_obs,
+            max_actions=max_actions, max_rank=max_rank,
             policy=L.POLICY[policy], block_actions=block_actions, resid_tol=resid_tol,
             pivot_tol=pivot_tol,
             prec=L.PREC[prec], smoother=1 if smoother else 0, sample_paths=sample_paths,
@@ -100,10 +103,10 @@ class CAKF:
         return L.cakf_state(self.ctx)[3]
 
     def state(self):
-        """(mean, factor) copies: float32 (n,) and (n, rank)."""
+        """(mean, factor) copies: float32 (N,) and (N, rank), N the state rows."""
         rank = self.rank
-        mean = torch.empty(self.n, dtype=torch.float32, device="cuda")
-        factor = torch.empty((self.n, max(rank, 1)), dtype=torch.float32, device="cuda")
+        mean = torch.empty(self.N, dtype=torch.float32, device="cuda")
+        factor = torch.empty((self.N, max(rank, 1)), dtype=torch.float32, device="cuda")
         L.cakf_copy_state(self.ctx, mean, factor, factor.shape[1])
         return mean, factor[:, :rank]
 

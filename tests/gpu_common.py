@@ -52,7 +52,7 @@ def oracle_run(cfg: Config, X, steps, actions, policy, pivot_tol=1e-10, resid_to
 
 
 def gpu_run(cfg: Config, X, steps, actions, policy, prec="fp32", probes=None,
-            pivot_tol=1e-10, resid_tol=0.0):
+            pivot_tol=1e-10, resid_tol=0.0, temporal="ou"):
     """Run the library step by step; returns per-step host results."""
     import torch
     from paper_2405_08971_amd.filter import CAKF, Record
@@ -65,7 +65,8 @@ def gpu_run(cfg: Config, X, steps, actions, policy, prec="fp32", probes=None,
     f = CAKF(Xd, nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid",
              lengthscale=cfg.ell, signal_var=cfg.sigma_f2, noise_var=cfg.noise_var,
              ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy=policy,
-             block_actions=block_actions, pivot_tol=pivot_tol, resid_tol=resid_tol, prec=prec)
+             block_actions=block_actions, pivot_tol=pivot_tol, resid_tol=resid_tol, prec=prec,
+             temporal=temporal)
     P = None if probes is None else torch.from_numpy(probes.astype(np.float32)).to(dev)
     out = []
     for k, item in enumerate(steps):
@@ -82,7 +83,8 @@ def gpu_run(cfg: Config, X, steps, actions, policy, prec="fp32", probes=None,
         mean, M = f.state()
         var = f.marginal_var()
         res = dict(mean=mean.cpu().numpy().astype(np.float64),
-                   var=var.cpu().numpy().astype(np.float64), rank=M.shape[1])
+                   var=var.cpu().numpy().astype(np.float64), rank=M.shape[1],
+                   rowsq=(M.double() ** 2).sum(1).cpu().numpy())
         if P is not None:
             res["MMt_probe"] = (M.double() @ (M.double().T @ P.double())).cpu().numpy()
         if rec is not None:
@@ -95,6 +97,7 @@ def gpu_run(cfg: Config, X, steps, actions, policy, prec="fp32", probes=None,
         f.truncate()
         Mp = f.state()[1]
         res["var_trunc"] = f.marginal_var().cpu().numpy().astype(np.float64)
+        res["rowsq_trunc"] = (Mp.double() ** 2).sum(1).cpu().numpy()
         res["rank_trunc"] = Mp.shape[1]
         out.append(res)
     torch.cuda.synchronize()
