@@ -72,15 +72,16 @@ def device_inputs(wl, ks):
     return out
 
 
-def make_filter(cfg, X, prec, policy="cg", block_actions=1):
+def make_filter(cfg, X, prec, policy="cg", block_actions=1, temporal="ou"):
     from paper_2405_08971_amd.filter import CAKF
     return CAKF(X, nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid",
                 lengthscale=cfg.ell, signal_var=cfg.sigma_f2, noise_var=cfg.noise_var,
-                ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r,
-                policy=policy, block_actions=block_actions, prec=prec)
+                ou_coeff=cfg.a, temporal=temporal, max_obs=cfg.m, max_actions=cfg.i,
+                max_rank=cfg.r, policy=policy, block_actions=block_actions, prec=prec)
 
 
-def run(cfg, X, inputs, warmup, steps, prec, breakdown=3, policy="cg", block_actions=1):
+def run(cfg, X, inputs, warmup, steps, prec, breakdown=3, policy="cg", block_actions=1,
+        temporal="ou"):
     """Warm-up steps, then the timed steps, then `breakdown` more steps with every phase
     timed (untimed as a whole).  In the timed steps only the dominant kernel's launches
     are bracketed by HIP events (each bracket costs a few microseconds on the stream).
@@ -89,7 +90,7 @@ def run(cfg, X, inputs, warmup, steps, prec, breakdown=3, policy="cg", block_act
     import torch
     from paper_2405_08971_amd.filter import Record
 
-    f = make_filter(cfg, X, prec, policy, block_actions)
+    f = make_filter(cfg, X, prec, policy, block_actions, temporal)
     nrec = warmup + steps + breakdown
     recs = [Record(cfg.m, cfg.i) for _ in range(nrec)]
     for k in range(warmup):
@@ -447,6 +448,17 @@ def main():
                                                              "block-residual actions")
         blk["note"] = "the same inputs as the headline run, timed the same way"
         line["next_rows"]["block_policy"] = blk
+        # the Matérn-3/2 temporal factor (2n-row state) on the same workload and inputs;
+        # its coefficient exp(-sqrt(3) dt / ell_t) is the OU coefficient at ell_t / sqrt(3)
+        cfg32 = cfg.replace(ell_t=cfg.ell_t / math.sqrt(3.0))
+        r32 = run(cfg32, X, inputs, args.warmup, args.steps, args.prec, breakdown=0,
+                  temporal="matern32")
+        line["next_rows"]["matern32_time"] = {
+            "workload": line["config"]["workload"] + ", Matern-3/2 temporal factor "
+                                                     "(state rows 2n)",
+            "value": args.steps / r32["elapsed"],
+            "ms_per_step": r32["elapsed"] / args.steps * 1e3,
+            "dropped_actions": r32["dropped"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, wl)
     print(json.dumps(line), flush=True)
