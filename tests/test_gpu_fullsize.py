@@ -9,6 +9,9 @@ covariance function on the same inputs:
   Ghat = Sigma_oo + noise_var I at the first step (one FP64 matrix-free product);
 * the block product on sampled state rows p: the new factor columns and the mean
   increment equal sigma_f2 K(x_p, Xo) [W w] - M^-[p] (Mo^T [W w]) (Alg. 2);
+* the truncation keeps the r leading directions of M M^T: the columns of M^+ are
+  mutually orthogonal with squared norms equal to the r largest eigenvalues of M^T M
+  (host LAPACK on the FP64 Gram of the GPU's untruncated factor);
 * marginal variances lie in [0, sigma_f2]; no action is dropped; the CG actions are
   numerically independent.  (In FP32 the recomputed residuals lose orthogonality in
   proportion to eps_32 |r0| / |rho_j|, which reaches 1e-1 once the residual has fallen by
@@ -26,6 +29,23 @@ pytestmark = pytest.mark.gpu
 
 def _rel(x, ref):
     return float(np.mean(np.abs(np.asarray(x) - ref)) / np.mean(np.abs(ref)))
+
+
+def check_truncation(M, Mplus, r):
+    """M: untruncated factor (device, FP32), Mplus: truncated (device).  The squared
+    column norms of M^+ are the r largest eigenvalues of M^T M and its columns are
+    mutually orthogonal (FP64 Grams of the device factors, host eigenvalues)."""
+    G = (M.double().T @ M.double()).cpu().numpy()
+    lam = np.sort(np.linalg.eigvalsh(0.5 * (G + G.T)))[::-1][:r]
+    Gp = (Mplus.double().T @ Mplus.double()).cpu().numpy()
+    d = np.sort(np.diag(Gp))[::-1]
+    e_val = float(np.max(np.abs(d - lam)) / lam[0])
+    off = Gp - np.diag(np.diag(Gp))
+    e_off = float(np.max(np.abs(off)) / lam[0])
+    kept = float(np.sum(d) / np.sum(lam))
+    print(f"  truncation: eigenvalue err {e_val:.2e}, off-diagonal {e_off:.2e}, "
+          f"kept trace ratio {kept:.8f}", flush=True)
+    assert e_val < 1e-5 and e_off < 1e-5 and abs(kept - 1.0) < 1e-6
 
 
 def test_full_size_step_properties():
@@ -96,4 +116,6 @@ def test_full_size_step_properties():
         print(f"  block product rel err on sampled rows {e:.2e}", flush=True)
         assert e < 1e-3
         f.truncate()
+        if M.shape[1] > cfg.r:
+            check_truncation(M, f.state()[1], cfg.r)
     f.close()

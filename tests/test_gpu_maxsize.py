@@ -1,0 +1,64 @@
+"""Largest workload (n = 262144 sphere points, Matern-3/2, m = 32768, i = 256 CG actions,
+r = 1024, 10% of the locations never observed, BF16X3 block product): the library's size
+limits (256 actions, rank 1024, the dense eigensolver path for K = r + i = 1280), checked
+by properties that hold at any size (see test_gpu_fullsize): kept actions, marginal
+variances in [0, sigma_f2], the block product on sampled state rows against the FP64
+covariance function, and the truncation's leading directions."""
+import numpy as np
+import pytest
+
+from oracle import matern
+from paper_2405_08971_amd.workload import CONFIGS, Workload
+from test_gpu_fullsize import _rel, check_truncation
+
+pytestmark = pytest.mark.gpu
+
+
+def test_max_size_step_properties():
+    import torch
+    from paper_2405_08971_amd.filter import CAKF, Record
+
+    cfg = CONFIGS["c5"]
+    wl = Workload(cfg, seed=0)
+    X32 = wl.X.astype(np.float32)
+    X64 = X32.astype(np.float64)
+    f = CAKF(torch.from_numpy(X32).cuda(), nu2=cfg.nu2, lengthscale=cfg.ell,
+             signal_var=cfg.sigma_f2, noise_var=cfg.noise_var, ou_coeff=cfg.a,
+             max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy="cg", prec="bf16x3")
+    rng = np.random.default_rng(1)
+    for k in range(1, 6):
+        idx, y = wl.step(k)
+        f.predict()
+        mean_pred, M_pred = f.state()
+        rec = Record(cfg.m, cfg.i)
+        f.update(torch.from_numpy(idx.astype(np.int32)).cuda(),
+                 torch.from_numpy(y.astype(np.float32)).cuda(), record=rec)
+        mean, M = f.state()
+        var = f.marginal_var().cpu().numpy()
+        torch.cuda.synchronize()
+        n_act = int(rec.n_actions.item())
+        print(f"step {k}: actions {n_act}, rank {M.shape[1]}, loglik {rec.loglik.item():.6e}, "
+              f"var [{var.min():.3e}, {var.max():.3e}]", flush=True)
+        assert n_act == cfg.i
+        assert np.isfinite(rec.loglik.item())
+        assert var.min() >= -1e-4 and var.max() <= cfg.sigma_f2 + 1e-4
+        if k == 2:
+            W = rec.W_obs.cpu().numpy().astype(np.float64)
+            w = rec.w_obs.cpu().numpy().astype(np.float64)
+            B = np.column_stack([W, w])
+            rows = np.sort(rng.choice(cfg.n, 128, replace=False))
+            Mp = M_pred.cpu().numpy().astype(np.float64)
+            ref = matern.gram(X64[rows], X64[idx], cfg.nu2, cfg.ell, cfg.sigma_f2) @ B
+            ref -= Mp[rows] @ (Mp[idx].T @ B)
+            Mn = M.cpu().numpy()
+            got = np.column_stack([Mn[rows, Mp.shape[1]:Mp.shape[1] + cfg.i],
+                                   mean.cpu().numpy()[rows] - mean_pred.cpu().numpy()[rows]])
+            e = _rel(got, ref)
+            print(f"  block product rel err on sampled rows {e:.2e}", flush=True)
+            assert e < 1e-3
+            del Mp, Mn
+        f.truncate()
+        if M.shape[1] > cfg.r:
+            check_truncation(M, f.state()[1], cfg.r)
+        del M, M_pred
+    f.close()
