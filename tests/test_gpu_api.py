@@ -1,0 +1,71 @@
+"""The C ABI's stopping rule, status words and argument checks on the device: the
+residual tolerance stops CG at the same action as the oracle; an observation index
+outside [0, n) is counted (and read as index 0) instead of faulting; calls that break
+the documented limits return an error before any work is queued."""
+import numpy as np
+import pytest
+
+from gpu_common import compare, gpu_run, inputs, oracle_run, small_config
+
+pytestmark = pytest.mark.gpu
+
+
+def test_residual_tolerance_stops_cg_like_the_oracle():
+    cfg = small_config("rtol", n=600, m=200, i=16, r=40, T=3)
+    X, steps, _ = inputs(cfg, seed=91, policy="cg")
+    # a tolerance the residual crosses well inside the budget at every step
+    model, recs = oracle_run(cfg, X, steps, None, "cg", resid_tol=0.2)
+    gpu = gpu_run(cfg, X, steps, [None] * cfg.T, "cg", "fp32", resid_tol=0.2)
+    errs = compare(cfg, model, recs, gpu)
+    for k, e in enumerate(errs, start=1):
+        print(f"step {k}: kept {e['n_actions']}, mean {e['mean']:.2e}, var {e['var']:.2e}",
+              flush=True)
+        assert e["n_actions"][0] == e["n_actions"][1]
+        assert 0 < e["n_actions"][1] < cfg.i
+        assert e["mean"] < 1e-4 and e["var"] < 1e-4
+
+
+def _filter(cfg, X, **kw):
+    import torch
+    from paper_2405_08971_amd.filter import CAKF
+    return CAKF(torch.from_numpy(X).cuda(), nu2=cfg.nu2, lengthscale=cfg.ell,
+                signal_var=cfg.sigma_f2, noise_var=cfg.noise_var, ou_coeff=cfg.a,
+                max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, **kw)
+
+
+def test_out_of_range_index_is_counted():
+    import torch
+    cfg = small_config("badidx", n=300, m=50, i=4, r=10, T=1)
+    X, steps, _ = inputs(cfg, seed=92, policy="cg")
+    idx, y = steps[0]
+    idx = idx.copy()
+    idx[7] = cfg.n + 5            # outside [0, n): read as index 0 and counted
+    f = _filter(cfg, X)
+    f.step(torch.from_numpy(idx).cuda(), torch.from_numpy(y).cuda())
+    dropped, nonfinite, bad = f.diagnostics()
+    var = f.marginal_var().cpu().numpy()
+    f.close()
+    assert bad == 1 and nonfinite == 0
+    assert np.all(np.isfinite(var))
+
+
+def test_limits_are_rejected_before_any_work():
+    import torch
+    cfg = small_config("limits", n=300, m=50, i=4, r=10, T=1)
+    X, steps, _ = inputs(cfg, seed=93, policy="cg")
+    idx, y = steps[0]
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        _filter(cfg, X, policy="block", block_actions=5)          # b > max_actions
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        _filter(cfg, X, policy="block", block_actions=2, resid_tol=0.1)
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        _filter(cfg, X, temporal="matern32", smoother=True)
+    f = _filter(cfg, X)
+    big = torch.zeros(cfg.m + 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        f.update(big, torch.zeros(cfg.m + 1, device="cuda"))      # m > max_obs
+    f.close()
+    g = _filter(cfg, X, policy="given")
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        g.update(torch.from_numpy(idx).cuda(), torch.from_numpy(y).cuda())  # no actions
+    g.close()
