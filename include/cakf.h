@@ -373,9 +373,10 @@ int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double* g
 
 /* Per-phase timing: phases is a bit mask (bit p times phase p; -1 = all phases, 0 =
  * off).  Enabling resets the counters and creates HIP events once (host-side objects,
- * no device memory); at most 2048 launches per phase are timed between reads.  Each
- * timed launch is bracketed by two events on the stream, which adds a few
- * microseconds per launch: time only the phases needed. */
+ * no device memory); at most 2048 launches per phase are timed between reads.  The
+ * SYM_TILES phase (one kernel per action) takes the launch's own start and stop
+ * timestamps; every other timed phase is bracketed by two events on the stream, which
+ * adds a few microseconds per launch: time only the phases needed. */
 #define CAKF_PROFILE_ALL (-1)
 int cakf_profile_enable(cakf_ctx* ctx, int phases);
 

@@ -141,6 +141,24 @@ struct PhaseTimer {
     }
 };
 
+// Timing of a phase that is one kernel launch: hands out the event pair, which the launch
+// stamps with its own start and stop times (hipExtLaunchKernel), so the figure is the
+// kernel's duration without the event packets around it.
+struct KernelTimer {
+    cakf_ctx* c;
+    int ph;
+    hipEvent_t start = nullptr, stop = nullptr;
+    KernelTimer(cakf_ctx* c_, int ph_) : c(c_), ph(ph_) {
+        if (c->prof.on && (c->prof.mask >> ph & 1) && c->prof.count[ph] < Prof::CAP) {
+            start = c->prof.ev[ph][0][c->prof.count[ph]];
+            stop = c->prof.ev[ph][1][c->prof.count[ph]];
+        }
+    }
+    ~KernelTimer() {
+        if (start) ++c->prof.count[ph];
+    }
+};
+
 void prof_free(cakf_ctx* c) {
     for (int p = 0; p < CAKF_PHASES; ++p)
         for (int k = 0; k < 2; ++k)
@@ -643,10 +661,10 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
                            c->mpart, c->cpart, c->gs, c->ls, st, &ncp);
     for (int j = 0; j < (block ? 0 : imax); ++j) {
         {
-            PhaseTimer t(c, CAKF_PHASE_SYM_TILES);
+            KernelTimer t(c, CAKF_PHASE_SYM_TILES);
             launch_sym_tiles(nu2, dist, c->Xo, c->S, d, j, c->part,
                              (cg && j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart, c->T,
-                             c->cpart, ncp, c->gs, c->colvec, c->ls, st);
+                             c->cpart, ncp, c->gs, c->colvec, c->ls, st, t.start, t.stop);
         }
         int nfu = 0;
         {

@@ -52,7 +52,8 @@ void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, floa
 void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
                       int j, float* part, const float* mpart, int nmpart, float* T,
                       const double* cpart, int ncpart, int gs, double* colvec,
-                      const LoopState* ls, hipStream_t st);
+                      const LoopState* ls, hipStream_t st, hipEvent_t ev_start = nullptr,
+                      hipEvent_t ev_stop = nullptr);
 void launch_form_u(const float* part, const float* S, float* U, const float* T,
                    const ObsDims& d, int j, double sigma_f2, double* fupart, double* ttv,
                    const LoopState* ls, hipStream_t st, int* nblk_out);

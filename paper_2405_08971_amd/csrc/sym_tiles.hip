@@ -3,6 +3,8 @@
 // tile serves its row block and, transposed, its column block), with the reductions of the
 // previous launch's column products in spare blocks.  Part of the observation-space loop
 // described in obs_loop.hip.
+#include <hip/hip_ext.h>
+
 #include "cakf_common.h"
 #include "launchers.h"
 
@@ -158,15 +160,17 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const float4* __restrict__ Xo
 void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
                       int j, float* part, const float* mpart, int nmpart, float* T,
                       const double* cpart, int ncpart, int gs, double* colvec,
-                      const LoopState* ls, hipStream_t st) {
+                      const LoopState* ls, hipStream_t st, hipEvent_t ev_start,
+                      hipEvent_t ev_stop) {
     const int nb = d.mp / SYM_TILE;
     const int tiles = nb * (nb + 1) / 2;
     const int n_t = (mpart && nmpart > 0) ? (d.rank + CR_POS - 1) / CR_POS : 0;
     const int n_c = (2 * j + 2 + CR_POS - 1) / CR_POS;
+    // with events: the launch's own start and stop timestamps (kernel duration only)
     CAKF_DISPATCH_KERNEL(nu2, dist,
-        hipLaunchKernelGGL((k_sym_tiles<NU2, DIST>), dim3(tiles + n_t + n_c), dim3(256), 0, st,
-                           Xo, S, d, j, part, mpart, nmpart, n_t, T, cpart, ncpart, gs, n_c,
-                           colvec, ls));
+        hipExtLaunchKernelGGL((k_sym_tiles<NU2, DIST>), dim3(tiles + n_t + n_c), dim3(256), 0,
+                              st, ev_start, ev_stop, 0, Xo, S, d, j, part, mpart, nmpart, n_t, T,
+                              cpart, ncpart, gs, n_c, colvec, ls));
 }
 
 }  // namespace cakf
