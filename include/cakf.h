@@ -244,6 +244,15 @@ int cakf_smooth_begin(cakf_ctx* ctx, const int32_t* idx, const float* w_obs,
 int cakf_smooth_step(cakf_ctx* ctx, const cakf_smooth_input* in, float* mean_out,
                      float* factor_out, int ld_out, float* var_out, int* out_rank);
 
+/* The whole backward pass (Alg. 3) over T recorded steps: steps[k] holds step k+1's
+ * filter output and record as for cakf_smooth_step (steps[T-1] may have pred_factor
+ * NULL: it is not read).  Writes the smoothed means and marginal variances of every
+ * step, row-major T x n (mean_out[k * n + p], var_out[k * n + p]; either may be NULL);
+ * step T's are the filter's.  Equivalent to cakf_smooth_begin with step T's record
+ * followed by cakf_smooth_step for k = T-1, ..., 1.  Needs cfg.smoother != 0. */
+int cakf_smooth(cakf_ctx* ctx, int T, const cakf_smooth_input* steps, float* mean_out,
+                float* var_out);
+
 /* Temporal interpolation (App. C, the corollary on temporal interpolation): the
  * filter's or the smoother's moments at a time t with t_k <= t < t_{k+1}, from step k's
  * filter moments (in->mean = m_k, in->factor = M_k untruncated; the other fields are not

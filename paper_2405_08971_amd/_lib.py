@@ -111,6 +111,7 @@ def lib() -> ctypes.CDLL:
             "cakf_smooth_begin": (i, [vp, vp, vp, vp, i]),
             "cakf_smooth_step": (i, [vp, ctypes.POINTER(cakf_smooth_input), vp, vp, i, vp,
                                      ctypes.POINTER(i)]),
+            "cakf_smooth": (i, [vp, i, ctypes.POINTER(cakf_smooth_input), vp, vp]),
             "cakf_interpolate": (i, [vp, ctypes.POINTER(cakf_smooth_input), d, d, i, vp, vp,
                                      i, vp, ctypes.POINTER(i)]),
             "cakf_sample_forward": (i, [vp, i, vp, vp, vp, ctypes.POINTER(cakf_sample_input),
@@ -277,3 +278,9 @@ def cakf_interpolate(ctx: int, inp: cakf_smooth_input, a_left: float, a_right: f
                                  ptr(mean_out), ptr(factor_out), ld_out, ptr(var_out),
                                  ctypes.byref(rank)), "cakf_interpolate")
     return rank.value
+
+
+def cakf_smooth(ctx: int, steps, mean_out=None, var_out=None) -> None:
+    """steps: a sequence of cakf_smooth_input, k = 1..T."""
+    arr = (cakf_smooth_input * len(steps))(*steps)
+    check(lib().cakf_smooth(ctx, len(steps), arr, ptr(mean_out), ptr(var_out)), "cakf_smooth")

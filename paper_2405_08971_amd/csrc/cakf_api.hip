@@ -1017,6 +1017,33 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 
+extern "C" int cakf_smooth(cakf_ctx* c, int T, const cakf_smooth_input* steps,
+                           float* mean_out, float* var_out) {
+    if (!c || !c->Xp || T < 1 || !steps) return CAKF_E_ARG;
+    const cakf_smooth_input& last = steps[T - 1];
+    if (!last.mean || last.rank < 0 || last.rank > c->Kmax ||
+        (last.rank > 0 && (!last.factor || last.ld < last.rank)))
+        return CAKF_E_ARG;
+    for (int k = 0; k + 1 < T; ++k)
+        if (!smooth_input_ok(c, &steps[k])) return CAKF_E_ARG;
+    const size_t n = c->n;
+    int rc = cakf_smooth_begin(c, last.idx, last.w_obs, last.W_obs, last.m);
+    if (rc) return rc;
+    // step T: the filter's moments
+    if (mean_out)
+        HIP_TRY(hipMemcpyAsync(mean_out + (T - 1) * n, last.mean, n * sizeof(float),
+                               hipMemcpyDeviceToDevice, c->stream));
+    if (var_out)
+        launch_marginal_var(last.factor, c->n, last.ld, last.rank, (float)c->cfg.signal_var,
+                            nullptr, c->n, var_out + (T - 1) * n, c->stream);
+    for (int k = T - 2; k >= 0; --k) {
+        rc = cakf_smooth_step(c, &steps[k], mean_out ? mean_out + k * n : nullptr, nullptr, 0,
+                              var_out ? var_out + k * n : nullptr, nullptr);
+        if (rc) return rc;
+    }
+    return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
 extern "C" int cakf_interpolate(cakf_ctx* c, const cakf_smooth_input* in, double a_left,
                                 double a_right, int smoothed, float* mean_out,
                                 float* factor_out, int ld_out, float* var_out, int* out_rank) {

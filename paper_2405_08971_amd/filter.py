@@ -137,6 +137,30 @@ class CAKF:
         else:
             L.cakf_smooth_begin(self.ctx, None, None, None, 0)
 
+    @staticmethod
+    def _smooth_input(mean, factor, pred_factor, idx, record):
+        m = 0 if idx is None else int(idx.numel())
+        return L.cakf_smooth_input(
+            mean=L.ptr(mean), factor=L.ptr(factor) if factor.shape[1] else None,
+            ld=max(factor.shape[1], 1), rank=factor.shape[1],
+            pred_factor=L.ptr(pred_factor) if pred_factor.shape[1] else None,
+            pred_ld=max(pred_factor.shape[1], 1), pred_rank=pred_factor.shape[1],
+            idx=L.ptr(idx) if m else None, w_obs=L.ptr(record.w_obs) if m else None,
+            W_obs=L.ptr(record.W_obs) if m else None, m=m)
+
+    def smooth(self, steps):
+        """The whole backward pass over steps = [(mean, factor, pred_factor, idx, record)]
+        (k = 1..T, as for smooth_step).  Returns the smoothed means and marginal
+        variances, both (T, n)."""
+        keep = [(s[0], s[1].contiguous(), s[2].contiguous()) for s in steps]
+        inp = [self._smooth_input(mean, fac, pf, s[3], s[4])
+               for (mean, fac, pf), s in zip(keep, steps)]
+        T = len(steps)
+        means = torch.empty((T, self.n), dtype=torch.float32, device="cuda")
+        var = torch.empty((T, self.n), dtype=torch.float32, device="cuda")
+        L.cakf_smooth(self.ctx, inp, means, var)
+        return means, var
+
     def smooth_step(self, mean, factor, pred_factor, idx=None, record: Optional[Record] = None,
                     want_factor: bool = False):
         """One backward step; factor / pred_factor are (n, rank) float32 device tensors.

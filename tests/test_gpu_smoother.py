@@ -39,3 +39,40 @@ def test_smoother_bf16x3_and_cg_policy():
         ev = rel_mean_err(gpu[k][1], sm[k].marginal_var(cfg.sigma_f2))
         print(f"step {k + 1}: mean {em:.2e} var {ev:.2e}", flush=True)
         assert em <= 1e-4 and ev <= 1e-4, (k, em, ev)
+
+
+def test_whole_backward_pass_entry_point():
+    """cakf_smooth (all steps in one call) against the oracle smoother."""
+    import torch
+    from paper_2405_08971_amd.filter import CAKF, Record
+    cfg = small_config("whole", n=500, m=160, i=6, r=10, T=5)
+    X, steps, actions = inputs(cfg, seed=23, missing_steps=(2,))
+    model, recs = oracle_run(cfg, X, steps, actions, "given")
+    sm = run_smoother(model, recs, cfg.r)
+    dev = "cuda"
+    f = CAKF(torch.from_numpy(X).to(dev), nu2=cfg.nu2, lengthscale=cfg.ell,
+             signal_var=cfg.sigma_f2, noise_var=cfg.noise_var, ou_coeff=cfg.a,
+             max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy="given", smoother=True)
+    fwd = []
+    for k, item in enumerate(steps):
+        f.predict()
+        _, Mp = f.state()
+        rec, idx = None, None
+        if item is None:
+            f.update(None, None)
+        else:
+            idx = torch.from_numpy(item[0]).to(dev)
+            rec = Record(len(item[0]), cfg.i)
+            f.update(idx, torch.from_numpy(item[1]).to(dev),
+                     torch.from_numpy(actions[k]).to(dev), rec)
+        mean, M = f.state()
+        fwd.append((mean, M, Mp, idx, rec))
+        f.truncate()
+    means, var = f.smooth(fwd)
+    means, var = means.cpu().numpy(), var.cpu().numpy()
+    f.close()
+    for k in range(cfg.T):
+        em = rel_mean_err(means[k], sm[k].m)
+        ev = rel_mean_err(var[k], sm[k].marginal_var(cfg.sigma_f2))
+        print(f"step {k + 1}: mean {em:.2e} var {ev:.2e}", flush=True)
+        assert em <= 1e-5 and ev <= 1e-5, (k, em, ev)
