@@ -26,13 +26,18 @@ CXXFLAGS = [
 ]
 
 
+# per-source additions: sym_tiles reads every MFMA result on the VALU at once, so its
+# accumulators are kept in architectural VGPRs (no copy out of the accumulation registers)
+EXTRA_FLAGS = {"sym_tiles.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *CXXFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CXXFLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")

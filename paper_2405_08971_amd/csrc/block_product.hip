@@ -44,13 +44,21 @@ __global__ __launch_bounds__(256) void k_block_fp32(const float4* __restrict__ X
         const int qn = min(BP_CHUNK, qend - q0);
         __syncthreads();
         if (tid < BP_CHUNK) xo[tid] = Xo[q0 + min(tid, qn - 1)];
-        // B chunk: qn rows x ncols columns into the [q][g][k] layout (zero padded)
-        for (int e = tid; e < BP_CHUNK * BP_COLS; e += 256) {
+        // B chunk: qn rows x ncols columns into the [q][g][k] layout (zero padded); all
+        // of a thread's loads are issued before the first store
+        constexpr int BLD = BP_CHUNK * BP_COLS / 256;
+        float bv[BLD];
+#pragma unroll
+        for (int u = 0; u < BLD; ++u) {
+            const int e = tid + 256 * u;
             const int q = e / BP_COLS, c = e % BP_COLS;
-            float v = 0.0f;
-            if (q < qn && c < ncols) v = B[(size_t)(q0 + q) * ldb + col0 + c];
-            float* dst = reinterpret_cast<float*>(&Bs[q][c & 3][0]);
-            dst[c >> 2] = v;
+            bv[u] = (q < qn && c < ncols) ? B[(size_t)(q0 + q) * ldb + col0 + c] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < BLD; ++u) {
+            const int e = tid + 256 * u;
+            const int q = e / BP_COLS, c = e % BP_COLS;
+            reinterpret_cast<float*>(&Bs[q][c & 3][0])[c >> 2] = bv[u];
         }
         __syncthreads();
 #pragma unroll
