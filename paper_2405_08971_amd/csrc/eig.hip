@@ -54,13 +54,16 @@ __device__ __forceinline__ double td_block_sum(double v, double* red) {
     return s;
 }
 
+// The arrival is a release (the workgroup's writes, ordered before it by the block
+// barrier, become visible at agent scope); the wait polls with relaxed loads and ends
+// with one acquire fence, so the cache invalidation of an acquire happens once per step
+// and not once per poll.
 __device__ __forceinline__ void td_barrier(unsigned* ctr, unsigned target, int* abort_flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             if (++spins > (1u << 24)) {
                 __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -68,7 +71,7 @@ __device__ __forceinline__ void td_barrier(unsigned* ctr, unsigned target, int* 
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
