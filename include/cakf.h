@@ -389,6 +389,12 @@ int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double* g
 #define CAKF_PROFILE_ALL (-1)
 int cakf_profile_enable(cakf_ctx* ctx, int phases);
 
+/* Time only every `every`-th launch of each timed phase (every >= 1; 1, the default,
+ * times every launch).  A sample of the launches keeps the event overhead out of most of
+ * a timed run; the counters and the launch count of cakf_profile_read cover the sampled
+ * launches only.  Takes effect from the next launch; CAKF_E_ARG for every < 1. */
+int cakf_profile_stride(cakf_ctx* ctx, int every);
+
 /* Total milliseconds and number of timed launches per phase since the last enable or
  * read (arrays of CAKF_PHASES entries), then reset the counters.  Synchronises the
  * stream. */

@@ -122,6 +122,7 @@ def lib() -> ctypes.CDLL:
             "cakf_loglik_grad": (i, [vp, i, ctypes.POINTER(cakf_tape_step),
                                      ctypes.POINTER(d)]),
             "cakf_profile_enable": (i, [vp, i]),
+            "cakf_profile_stride": (i, [vp, i]),
             "cakf_profile_read": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(i)]),
         }
         for name, (res, args) in sigs.items():
@@ -215,6 +216,10 @@ def cakf_diagnostics(ctx: int):
 
 def cakf_profile_enable(ctx: int, on: int) -> None:
     check(lib().cakf_profile_enable(ctx, int(on)), "cakf_profile_enable")
+
+
+def cakf_profile_stride(ctx: int, every: int) -> None:
+    check(lib().cakf_profile_stride(ctx, int(every)), "cakf_profile_stride")
 
 
 def cakf_profile_read(ctx: int):

@@ -34,6 +34,8 @@ struct Prof {
     hipEvent_t* ev[CAKF_PHASES][2];
     int count[CAKF_PHASES];
     int mask;           // bit p: phase p is timed
+    int stride;         // time every stride-th launch of a timed phase (>= 1)
+    int seen[CAKF_PHASES];
     bool on;
 };
 
@@ -126,15 +128,23 @@ struct cakf_ctx {
 
 namespace {
 
+// Whether this launch of phase ph is timed (the phase is enabled, this launch falls on
+// the sampling stride and an event pair is free).
+bool prof_take(cakf_ctx* c, int ph) {
+    if (!c->prof.on || !(c->prof.mask >> ph & 1)) return false;
+    const bool on_stride = c->prof.seen[ph]++ % c->prof.stride == 0;
+    return on_stride && c->prof.count[ph] < Prof::CAP;
+}
+
 struct PhaseTimer {
     cakf_ctx* c;
     int ph;
-    PhaseTimer(cakf_ctx* c_, int ph_) : c(c_), ph(ph_) {
-        if (c->prof.on && (c->prof.mask >> ph & 1) && c->prof.count[ph] < Prof::CAP)
-            (void)hipEventRecord(c->prof.ev[ph][0][c->prof.count[ph]], c->stream);
+    bool take;
+    PhaseTimer(cakf_ctx* c_, int ph_) : c(c_), ph(ph_), take(prof_take(c_, ph_)) {
+        if (take) (void)hipEventRecord(c->prof.ev[ph][0][c->prof.count[ph]], c->stream);
     }
     ~PhaseTimer() {
-        if (c->prof.on && (c->prof.mask >> ph & 1) && c->prof.count[ph] < Prof::CAP) {
+        if (take) {
             (void)hipEventRecord(c->prof.ev[ph][1][c->prof.count[ph]], c->stream);
             ++c->prof.count[ph];
         }
@@ -149,7 +159,7 @@ struct KernelTimer {
     int ph;
     hipEvent_t start = nullptr, stop = nullptr;
     KernelTimer(cakf_ctx* c_, int ph_) : c(c_), ph(ph_) {
-        if (c->prof.on && (c->prof.mask >> ph & 1) && c->prof.count[ph] < Prof::CAP) {
+        if (prof_take(c, ph)) {
             start = c->prof.ev[ph][0][c->prof.count[ph]];
             stop = c->prof.ev[ph][1][c->prof.count[ph]];
         }
@@ -249,6 +259,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     cakf_ctx* c = new (std::nothrow) cakf_ctx;
     if (!c) return CAKF_E_NOMEM;
     std::memset(c, 0, sizeof(*c));
+    c->prof.stride = 1;
     c->cfg = *cfg;
     c->stream = (hipStream_t)cfg->stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -1209,7 +1220,13 @@ extern "C" int cakf_profile_enable(cakf_ctx* c, int on) {
             }
         c->prof.on = true;
     }
-    for (int p = 0; p < CAKF_PHASES; ++p) c->prof.count[p] = 0;
+    for (int p = 0; p < CAKF_PHASES; ++p) c->prof.count[p] = c->prof.seen[p] = 0;
+    return CAKF_OK;
+}
+
+extern "C" int cakf_profile_stride(cakf_ctx* c, int every) {
+    if (!c || every < 1) return CAKF_E_ARG;
+    c->prof.stride = every;
     return CAKF_OK;
 }
 
@@ -1226,7 +1243,7 @@ extern "C" int cakf_profile_read(cakf_ctx* c, double* total_ms, int* launches) {
         }
         total_ms[p] = acc;
         launches[p] = n;
-        if (c->prof.on) c->prof.count[p] = 0;
+        if (c->prof.on) c->prof.count[p] = c->prof.seen[p] = 0;
     }
     return CAKF_OK;
 }

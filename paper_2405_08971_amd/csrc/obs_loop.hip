@@ -150,6 +150,7 @@ void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, floa
 // TT_COLS-wide column blocks after the row blocks compute (T^T t_j)_l = t_l^T t_j for
 // l <= j (FP64), one wave per column group.
 constexpr int FU_ROWS = 64;
+constexpr int FU_LOADS = 8;
 constexpr int TT_COLS = 16;
 
 __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
@@ -197,45 +198,46 @@ __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
         }
         return;
     }
-    __shared__ double ured[4][FU_ROWS];
+    // rows: thread (quad, grp) sums rows 4 quad .. 4 quad + 3 of the block over the slots
+    // grp, grp + 16, ... with 16-byte loads, FU_LOADS slots in flight at a time; the 16
+    // slot groups are then combined in a fixed order
+    __shared__ double ured[16][FU_ROWS + 1];
     const int nb = d.mp / SYM_TILE;
-    const int row = tid & 63, grp = tid >> 6;
-    const int p = blockIdx.x * FU_ROWS + row;
-    double a8[8];
+    const int quad = tid & 15, grp = tid >> 4;
+    const int p0 = blockIdx.x * FU_ROWS + 4 * quad;    // < mp (mp a multiple of 128)
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = grp; s0 < nb; s0 += 16 * FU_LOADS) {
+        float4 v[FU_LOADS];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a8[u] = 0.0;
-    float sj = 0.0f;
-    if (p < d.m) {
-        if (grp == 0) sj = S[(size_t)p * d.imax + j];
-        int sl = grp;
-        for (; sl + 60 < nb; sl += 64) {
-            float v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = part[(size_t)(sl + 4 * u) * d.mp + p];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) a8[u & 7] += (double)v[u];
+        for (int u = 0; u < FU_LOADS; ++u) {
+            const int sl = s0 + 16 * u;
+            v[u] = sl < nb ? *reinterpret_cast<const float4*>(part + (size_t)sl * d.mp + p0)
+                           : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
-        for (; sl + 28 < nb; sl += 32) {
-            float v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(sl + 4 * u) * d.mp + p];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) a8[u] += (double)v[u];
+        for (int u = 0; u < FU_LOADS; ++u) {
+            a4[0] += (double)v[u].x;
+            a4[1] += (double)v[u].y;
+            a4[2] += (double)v[u].z;
+            a4[3] += (double)v[u].w;
         }
-        for (; sl < nb; sl += 4) a8[0] += part[(size_t)sl * d.mp + p];
     }
-    ured[grp][row] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ured[grp][4 * quad + r] = a4[r];
     __syncthreads();
-    if (grp == 0) {
+    if (tid < FU_ROWS) {
+        const int p = blockIdx.x * FU_ROWS + tid;
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) t += ured[g][tid];
         double prod = 0.0;
         if (p < d.m) {
-            const float uf = (float)(sigma_f2 * ((ured[0][row] + ured[1][row]) +
-                                                 (ured[2][row] + ured[3][row])));
+            const float uf = (float)(sigma_f2 * t);
             U[(size_t)p * d.imax + j] = uf;
-            prod = (double)sj * (double)uf;
+            prod = (double)S[(size_t)p * d.imax + j] * (double)uf;
         }
         prod = wave_sum(prod);
-        if (row == 0) fupart[blockIdx.x] = prod;
+        if (tid == 0) fupart[blockIdx.x] = prod;
     }
 }
 

@@ -258,8 +258,9 @@ class CAKF:
         (a sequence of cakf_tape_step; see paper_2405_08971_amd.autograd)."""
         return L.cakf_loglik_grad(self.ctx, tape)
 
-    def profile(self, on=True):
-        """on: True (all phases), False (off), or an iterable of phase names."""
+    def profile(self, on=True, every=1):
+        """on: True (all phases), False (off), or an iterable of phase names; every: time
+        only every every-th launch of each timed phase."""
         if on is True:
             mask = -1
         elif not on:
@@ -269,6 +270,7 @@ class CAKF:
             for name in on:
                 mask |= 1 << L.PHASES.index(name)
         L.cakf_profile_enable(self.ctx, mask)
+        L.cakf_profile_stride(self.ctx, every)
 
     def profile_read(self):
         return L.cakf_profile_read(self.ctx)
