@@ -7,16 +7,25 @@
 namespace cakf {
 
 constexpr int GT = 64;        // Gram tile side
-constexpr int GROWS = 32;     // factor rows staged per LDS chunk
+constexpr int GROWS = 64;     // factor rows staged per LDS chunk
+constexpr int GLD = GT + 16;  // LDS row stride (floats): a wave's 4 x 16 operand reads
+                              // fall on distinct banks
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Partial Gram tiles: block (tile, split) accumulates M[rows, c-block]^T M[rows, d-block]
 // over its row range in FP64 (FP32 inputs; each product is exact in FP64), for
-// lower-triangle tiles c-block >= d-block.  Each thread owns a 4 x 4 set of outputs and
-// reads one float4 of each operand per staged row.
+// lower-triangle tiles c-block >= d-block.  The products run on FP64 MFMA
+// (v_mfma_f64_16x16x4f64, D = A B + D over 4 factor rows): wave w owns the 32 x 32
+// quarter at rows 32 (w / 2), columns 32 (w % 2) of the 64 x 64 tile as 2 x 2 products.
+// Lane l supplies A[l % 16][l / 16] = M[row l / 16, column l % 16 of the c sub-block]
+// and B[l / 16][l % 16] = M[row l / 16, column l % 16 of the d sub-block], widened to
+// FP64, and holds D[l / 16 + 4 i][l % 16] in register i (rows interleaved by 4, unlike
+// the FP32 16 x 16 x 4 form).
 __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ M, int n,
                                                       int ldM, int K, int nsplit,
                                                       double* __restrict__ work) {
-    __shared__ float As[GROWS][GT + 4], Bs[GROWS][GT + 4];
+    __shared__ float As[GROWS][GLD], Bs[GROWS][GLD];
     const int tile = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
     int tc = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
     while ((tc + 1) * (tc + 2) / 2 <= tile) ++tc;
@@ -26,47 +35,84 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
     const int rows_per = (n + nsplit - 1) / nsplit;
     const int r0 = split * rows_per, r1 = min(n, r0 + rows_per);
     const int tid = threadIdx.x;
-    const int ti = tid >> 4, tj = tid & 15;
-    double acc[4][4];
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int cb = 32 * (w >> 1), db = 32 * (w & 1);
+    f64x4 acc[2][2];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[x][y][i] = 0.0;
+    // staging: 16-byte loads (factor rows are 16-byte aligned, ldM a multiple of 4), the
+    // next chunk's loads issued into registers before the current chunk's products
+    constexpr int LD4 = GROWS * GT / 4 / 256;      // float4 loads per operand per thread
+    float4 ra[LD4], rb[LD4];
+    auto load_chunk = [&](int p0) {
+#pragma unroll
+        for (int u = 0; u < LD4; ++u) {
+            const int e = tid + 256 * u;
+            const int rr = e / (GT / 4), c4 = 4 * (e % (GT / 4));
+            const int p = p0 + rr;
+            float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+            if (p < r1) {
+                if (c0 + c4 < K) a = *reinterpret_cast<const float4*>(M + (size_t)p * ldM + c0 + c4);
+                if (d0 + c4 < K) b = *reinterpret_cast<const float4*>(M + (size_t)p * ldM + d0 + c4);
+            }
+            // columns at or beyond K (inside the row's 16-byte group) read as zero
+            if (c0 + c4 + 3 >= K) {
+                if (c0 + c4 + 1 >= K) a.y = 0.0f;
+                if (c0 + c4 + 2 >= K) a.z = 0.0f;
+                a.w = 0.0f;
+            }
+            if (d0 + c4 + 3 >= K) {
+                if (d0 + c4 + 1 >= K) b.y = 0.0f;
+                if (d0 + c4 + 2 >= K) b.z = 0.0f;
+                b.w = 0.0f;
+            }
+            ra[u] = a;
+            rb[u] = b;
+        }
+    };
+    if (r0 < r1) load_chunk(r0);
     for (int p0 = r0; p0 < r1; p0 += GROWS) {
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < GROWS * GT / 256; ++u) {
+        for (int u = 0; u < LD4; ++u) {
             const int e = tid + 256 * u;
-            const int rr = e / GT, cc = e % GT;
-            const int p = p0 + rr;
-            const bool okr = p < r1;
-            As[rr][cc] = (okr && c0 + cc < K) ? M[(size_t)p * ldM + c0 + cc] : 0.0f;
-            Bs[rr][cc] = (okr && d0 + cc < K) ? M[(size_t)p * ldM + d0 + cc] : 0.0f;
+            const int rr = e / (GT / 4), c4 = 4 * (e % (GT / 4));
+            *reinterpret_cast<float4*>(&As[rr][c4]) = ra[u];
+            *reinterpret_cast<float4*>(&Bs[rr][c4]) = rb[u];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < GROWS; ++rr) {
-            const float4 a = *reinterpret_cast<const float4*>(&As[rr][4 * ti]);
-            const float4 b = *reinterpret_cast<const float4*>(&Bs[rr][4 * tj]);
-            const double av[4] = {a.x, a.y, a.z, a.w};
-            const double bv[4] = {b.x, b.y, b.z, b.w};
+        if (p0 + GROWS < r1) load_chunk(p0 + GROWS);
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+        for (int ks = 0; ks < GROWS / 4; ++ks) {
+            const int rr = 4 * ks + lk;
+            double a[2], b[2];
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_fma(av[x], bv[y], acc[x][y]);
+            for (int x = 0; x < 2; ++x) a[x] = (double)As[rr][cb + 16 * x + li];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) b[y] = (double)Bs[rr][db + 16 * y + li];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
         }
     }
-    double* w = work + (size_t)split * K * K;
+    double* wk = work + (size_t)split * K * K;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        const int c = c0 + 4 * ti + x;
-        if (c >= K) continue;
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int dd = d0 + 4 * tj + y;
-            if (dd < K) w[(size_t)c * K + dd] = acc[x][y];
-        }
-    }
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = c0 + cb + 16 * x + lk + 4 * i;
+                const int dd = d0 + db + 16 * y + li;
+                if (c < K && dd < K) wk[(size_t)c * K + dd] = acc[x][y][i];
+            }
 }
 
 // G = sum over splits (fixed order), lower tiles mirrored to the full symmetric matrix.
@@ -84,6 +130,8 @@ __global__ void k_gram_reduce(const double* __restrict__ work, int K, int nsplit
     }
 }
 
+// M must be 16-byte aligned with ldM a multiple of 4 (true of every factor buffer: device
+// allocations with leading dimensions rounded up to 4), and K <= ldM.
 void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* work,
                    size_t work_elems, hipStream_t st) {
     const int nt = (K + GT - 1) / GT;
