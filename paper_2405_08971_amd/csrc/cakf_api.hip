@@ -696,7 +696,7 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
             nmpart = ncp;
         }
     }
-    launch_build_block(c->S, c->Linv, c->beta, d, c->B, c->bp, c->bp, rec->W_obs, rec->w_obs,
+    launch_build_block(c->S, c->LinvT, c->beta, d, c->B, c->bp, c->bp, rec->W_obs, rec->w_obs,
                        rec->S, c->ls, st);
     const int b = c->imax + 1;
     if (d.rank > 0) {

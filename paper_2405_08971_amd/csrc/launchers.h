@@ -76,7 +76,7 @@ void launch_next_action(int resid, const float* U, const float* Mo, const float*
                         float* V, const double* beta, const float* T, float noise_var,
                         const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
                         const LoopState* ls, hipStream_t st, int* nblk_out);
-void launch_build_block(const float* S, const double* Linv, const double* beta,
+void launch_build_block(const float* S, const double* LinvT, const double* beta,
                         const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
                         float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st);
 void launch_finish_record(const LoopState* ls, const double* L, const double* Linv, int imax,

@@ -895,7 +895,7 @@ void launch_round_mot(const float* Mo, const float* S, const ObsDims& d, int j0,
 // B = [S L^{-T} | S beta | 0] (mp x bp, row-major) for the block product, plus the
 // optional record copies (m rows).  FP64 accumulation.
 __global__ __launch_bounds__(256) void k_build_block(const float* __restrict__ S,
-                                                     const double* __restrict__ Linv,
+                                                     const double* __restrict__ LinvT,
                                                      const double* __restrict__ beta,
                                                      ObsDims d, float* __restrict__ B,
                                                      int ldb, int bp,
@@ -912,8 +912,10 @@ __global__ __launch_bounds__(256) void k_build_block(const float* __restrict__ S
         double acc = 0.0;
         if (p < d.m) {
             if (c < d.imax) {
-                const double* Lrow = Linv + (size_t)c * d.imax;
-                for (int l = 0; l <= c; ++l) acc = __builtin_fma((double)Srow[l], Lrow[l], acc);
+                // (L^{-1})[c][l] = LinvT[l][c]: consecutive lanes (columns c) read
+                // consecutive words
+                for (int l = 0; l <= c; ++l)
+                    acc = __builtin_fma((double)Srow[l], LinvT[(size_t)l * d.imax + c], acc);
             } else if (c == d.imax) {
                 for (int l = 0; l < d.imax; ++l) acc = __builtin_fma((double)Srow[l], beta[l], acc);
             }
@@ -931,12 +933,12 @@ __global__ __launch_bounds__(256) void k_build_block(const float* __restrict__ S
     }
 }
 
-void launch_build_block(const float* S, const double* Linv, const double* beta,
+void launch_build_block(const float* S, const double* LinvT, const double* beta,
                         const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
                         float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st) {
     const size_t total = (size_t)d.mp * bp;
     const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_build_block, dim3(blocks), dim3(256), 0, st, S, Linv, beta, d, B, ldb,
+    hipLaunchKernelGGL(k_build_block, dim3(blocks), dim3(256), 0, st, S, LinvT, beta, d, B, ldb,
                        bp, rec_W, rec_w, rec_S, ls);
 }
 
