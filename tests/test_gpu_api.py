@@ -1,7 +1,8 @@
-"""The C ABI's stopping rule, status words and argument checks on the device: the
-residual tolerance stops CG at the same action as the oracle; an observation index
-outside [0, n) is counted (and read as index 0) instead of faulting; calls that break
-the documented limits return an error before any work is queued."""
+"""The C ABI's stopping rule, status words, argument checks and profiler sampling on the
+device: the residual tolerance stops CG at the same action as the oracle; an observation
+index outside [0, n) is counted (and read as index 0) instead of faulting; calls that
+break the documented limits return an error before any work is queued; a sampling stride
+times every k-th launch of a phase."""
 import numpy as np
 import pytest
 
@@ -69,3 +70,28 @@ def test_limits_are_rejected_before_any_work():
     with pytest.raises(RuntimeError, match="invalid argument"):
         g.update(torch.from_numpy(idx).cuda(), torch.from_numpy(y).cuda())  # no actions
     g.close()
+
+
+def test_profile_stride_times_every_kth_launch():
+    import torch
+    from paper_2405_08971_amd import _lib as L
+    cfg = small_config("stride", n=300, m=60, i=8, r=20, T=2)
+    X, steps, _ = inputs(cfg, seed=94, policy="cg")
+    f = _filter(cfg, X)
+    # one update runs i = 8 action-loop matvecs: every 3rd of them is timed (0, 3, 6)
+    f.profile(["sym_tiles", "tail"], every=3)
+    idx, y = steps[0]
+    f.step(torch.from_numpy(idx).cuda(), torch.from_numpy(y).cuda())
+    prof = f.profile_read()
+    assert prof["sym_tiles"][1] == 3 and prof["tail"][1] == 3
+    assert prof["sym_tiles"][0] > 0.0
+    assert prof["form_u"][1] == 0                      # not enabled
+    # reading resets the counters and the sampling phase
+    f.profile(["sym_tiles"], every=1)
+    idx, y = steps[1]
+    f.step(torch.from_numpy(idx).cuda(), torch.from_numpy(y).cuda())
+    assert f.profile_read()["sym_tiles"][1] == cfg.i
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        L.cakf_profile_stride(f.ctx, 0)
+    f.profile(False)
+    f.close()
