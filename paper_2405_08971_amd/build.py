@@ -26,9 +26,11 @@ CXXFLAGS = [
 ]
 
 
-# per-source additions: sym_tiles reads every MFMA result on the VALU at once, so its
-# accumulators are kept in architectural VGPRs (no copy out of the accumulation registers)
-EXTRA_FLAGS = {"sym_tiles.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# per-source additions: sym_tiles and the block product read FP32 MFMA results (squared
+# distances) on the VALU, so MFMA results are kept in architectural VGPRs (no copy out of
+# the accumulation registers)
+EXTRA_FLAGS = {"sym_tiles.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+               "block_product.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():

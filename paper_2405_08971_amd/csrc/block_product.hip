@@ -152,8 +152,24 @@ static void launch_fp32_cols(int cpt, dim3 grid, hipStream_t st, const float4* X
 // tiles.  With X3 the products are
 // Kh Bh + Kl Bh + Kh Bl on K = Kh + Kl, B = Bh + Bl (each part BF16), which restores
 // close to FP32 accuracy at 3x the MFMA work.
+//
+// For the Euclidean Matern-3/2 and -5/2 kernels (MD) the squared scaled distances come from
+// FP32 MFMA instead of the VALU: v_mfma_f32_32x32x2f32 twice (coordinates x, y, then z and
+// the norm term) per 32 observations gives D'[o][p] = <(c x_o, c y_o, c z_o, c^2 |x_o|^2),
+// (-2 c x_p, -2 c y_p, -2 c z_p, 1)> + c^2 |x_p|^2 with the observations as rows, so lane l
+// receives its own state row l % 32 against the observations
+// 8 (i / 4) + 4 (l / 32) + i % 4 (i = 0..15) of the group.  Taken 8 at a time these are the
+// lane's A values for two BF16 k-steps, in the observation order that swaps the middle two
+// 4-blocks of every 16 (positions 4..7 <-> 8..11); B is stored in that order (k_split_bt),
+// so the products are unchanged.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// observation at stored position q of the MD order (an involution within blocks of 16)
+__host__ __device__ __forceinline__ int md_perm(int q) {
+    const int o = q & 15;
+    return ((o >> 2) == 1 || (o >> 2) == 2) ? (q ^ 12) : q;
+}
 constexpr int MF_KC = 64;        // observations per LDS chunk (4 MFMA k-steps)
 constexpr int MF_ROWS = 128;     // state rows per workgroup (4 waves x 32)
 
@@ -172,6 +188,9 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
     const int rl = lane & 31, half = lane >> 5;
     const int row0 = blockIdx.x * MF_ROWS + w * 32;
     const float4 xa = prep_row<DIST>(Xs[min(row0 + rl, n - 1)]);
+    constexpr bool MD = DIST == DIST_EUCLID && NU2 != 1;
+    // MD operands of the state-row side: coordinates (half, 2 + half) of the prepared row
+    const float rb1 = half == 0 ? xa.x : xa.y, rb2 = half == 0 ? xa.z : 1.0f;
     f32x16 acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c)
@@ -190,14 +209,34 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
             if constexpr (X3) bl[c][g] = *reinterpret_cast<const bf16x8*>(Btl + off);
         }
         __syncthreads();
+        f32x16 dd;
 #pragma unroll
         for (int ks = 0; ks < MF_KC / 16; ++ks) {
             bf16x8 ah, al;
+            if constexpr (MD) {
+                if (ks % 2 == 0) {
+                    // squared distances of the 32 observations of k-steps ks, ks + 1
+                    const float4 xg = xo[ks * 16 + rl];
+                    const float a1 = half == 0 ? xg.x : xg.y, a2 = half == 0 ? xg.z : xg.w;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float ka = kval<NU2, DIST>(xa, xo[ks * 16 + 8 * half + t]);
-                ah[t] = (__bf16)ka;
-                if constexpr (X3) al[t] = (__bf16)(ka - (float)ah[t]);
+                    for (int i = 0; i < 16; ++i) dd[i] = xa.w;
+                    dd = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, rb1, dd, 0, 0, 0);
+                    dd = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, rb2, dd, 0, 0, 0);
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const float ka =
+                        matern_u<NU2>(__builtin_amdgcn_sqrtf(__builtin_fabsf(dd[8 * (ks % 2) + t])));
+                    ah[t] = (__bf16)ka;
+                    if constexpr (X3) al[t] = (__bf16)(ka - (float)ah[t]);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const float ka = kval<NU2, DIST>(xa, xo[ks * 16 + 8 * half + t]);
+                    ah[t] = (__bf16)ka;
+                    if constexpr (X3) al[t] = (__bf16)(ka - (float)ah[t]);
+                }
             }
             // the three products of each column tile are issued NT apart, so that no
             // MFMA waits on the result of the one before it
@@ -248,14 +287,15 @@ static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const 
 }
 
 // Split B (FP32, row-major mp x ldb, columns 0..bp) into transposed BF16 parts:
-// Bth[c * mp + q] = bf16(B[q, c]), Btl = bf16(B - Bth).
+// Bth[c * mp + q] = bf16(B[o, c]), Btl = bf16(B - Bth), o = q or, with perm, md_perm(q).
 __global__ void k_split_bt(const float* __restrict__ B, int mp, int ldb, int bcols, int bp,
-                           __bf16* __restrict__ Bth, __bf16* __restrict__ Btl) {
+                           int perm, __bf16* __restrict__ Bth, __bf16* __restrict__ Btl) {
     const size_t total = (size_t)mp * bp;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(e / mp), q = (int)(e % mp);
-        const float v = c < bcols ? B[(size_t)q * ldb + c] : 0.0f;
+        const int o = perm ? md_perm(q) : q;
+        const float v = c < bcols ? B[(size_t)o * ldb + c] : 0.0f;
         const __bf16 h = (__bf16)v;
         Bth[e] = h;
         Btl[e] = (__bf16)(v - (float)h);
@@ -314,7 +354,8 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
         const int ntiles = (bcols + 31) / 32;
         const size_t total = (size_t)mp * ntiles * 32;
         hipLaunchKernelGGL(k_split_bt, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
-                           dim3(256), 0, st, B, mp, ldb, bcols, ntiles * 32, Bth, Btl);
+                           dim3(256), 0, st, B, mp, ldb, bcols, ntiles * 32,
+                           (dist == DIST_EUCLID && nu2 != 1) ? 1 : 0, Bth, Btl);
         for (int t0 = 0; t0 < ntiles; t0 += 5) {
             const int nt = std::min(5, ntiles - t0);
             if (prec == 2) {
