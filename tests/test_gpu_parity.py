@@ -119,8 +119,10 @@ def test_deterministic_bitwise():
 PREC_TOL = {"bf16": 1e-2, "bf16x3": 1e-4}
 
 
+# Euclidean Matern-3/2 and -5/2 take the squared distances of the kernel tile from FP32
+# MFMA; Matern-1/2 and the great-circle distance evaluate the tile on the VALU.
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
-@pytest.mark.parametrize("case", ["sphere_m32", "plane_m52"])
+@pytest.mark.parametrize("case", ["sphere_m32", "plane_m52", "plane_m12", "sphere_m12_geodesic"])
 def test_given_actions_bf16_block_product_matches_oracle(case, prec):
     cfg = small_config(case, **CASES[case])
     X, steps, actions = inputs(cfg, seed=8, missing_steps=(3,) if cfg.T >= 5 else ())
