@@ -765,9 +765,10 @@ static int truncate_factor(cakf_ctx* c, const float* M, int rows, int ld, int K,
         PhaseTimer t(c, CAKF_PHASE_ROTATE);
         if (!picked) launch_pick_rotation(c->G, K, r, c->Vr, rotation, st);
         const float one = 1.0f, zero = 0.0f;
-        // Mout (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n)
-        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, r,
-                               rows, K, &one, c->Vr, K, M, ld, &zero, Mout, ldo));
+        // Mout (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n),
+        // V_r row-major K x r being V_r^T column-major (no transposed operand)
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_none, r, rows,
+                               K, &one, c->Vr, r, M, ld, &zero, Mout, ldo));
     }
     return CAKF_OK;
 }

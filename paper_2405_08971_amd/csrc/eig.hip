@@ -222,7 +222,7 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
 // Z's column K - 1 - c; the reflectors are applied last-to-first, z <- z - tau_j v_j
 // (v_j^T z).  Each wave keeps two columns in registers (lane l holds rows l + 64 u); a
 // workgroup stages BT_CHUNK reflectors at a time in LDS for its four waves.  Writes
-// Vr (FP32, column-major K x r) and, if asked, rot (FP64, row-major K x r).
+// Vr (FP32, row-major K x r) and, if asked, rot (FP64, row-major K x r).
 constexpr int BT_CHUNK = 8;
 
 template <int U>
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_backtransform(const double* __restrict_
         for (int u = 0; u < U; ++u) {
             const int k = lane + 64 * u;
             if (k < K) {
-                Vr[(size_t)c * K + k] = (float)z[q][u];
+                Vr[(size_t)k * r + c] = (float)z[q][u];
                 if (rot) rot[(size_t)k * r + c] = z[q][u];
             }
         }

@@ -148,7 +148,7 @@ void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* wor
 
 // The eigensolver returns eigenvalues in ascending order with eigenvectors as columns
 // of E (column-major K x K).  V_r keeps the r leading ones in descending order:
-// Vr (FP32, column-major K x r) and, optionally, rot_out (FP64, row-major K x r).
+// Vr (FP32, row-major K x r) and, optionally, rot_out (FP64, row-major K x r).
 __global__ void k_pick_rotation(const double* __restrict__ E, int K, int r,
                                 float* __restrict__ Vr, double* __restrict__ rot_out) {
     const size_t total = (size_t)K * r;
@@ -156,7 +156,7 @@ __global__ void k_pick_rotation(const double* __restrict__ E, int K, int r,
          e += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(e / K), k = (int)(e % K);
         const double v = E[(size_t)(K - 1 - c) * K + k];
-        Vr[(size_t)c * K + k] = (float)v;
+        Vr[(size_t)k * r + c] = (float)v;
         if (rot_out) rot_out[(size_t)k * r + c] = v;
     }
 }
