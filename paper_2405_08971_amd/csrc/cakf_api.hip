@@ -299,7 +299,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     rc |= dalloc(&c->colvec, (size_t)c->gs);
     rc |= dalloc(&c->fupart, (size_t)(c->mpmax / 64));
     rc |= dalloc(&c->ttpart, (size_t)c->imax);
-    rc |= dalloc(&c->mpart, (size_t)std::max(nablk, (c->mmax + 255) / 256) * c->ldmo);
+    rc |= dalloc(&c->mpart, (size_t)std::max(nablk, (c->mmax + 63) / 64) * c->ldmo);
     rc |= dalloc(&c->Linv, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->LinvT, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->L, (size_t)c->imax * c->imax);

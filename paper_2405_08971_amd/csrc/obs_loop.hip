@@ -86,7 +86,10 @@ void launch_gather(const float4* Xs, int n, const float* mean, const float* M, i
 }
 
 // ------------------------------------------------------------- column sums A^T x (det.)
-// partial[b, c] = sum over the 256 rows of block b of A[p, c] * x[p].
+// partial[b, c] = sum over the CS_ROWS rows of block b of A[p, c] * x[p] (cols <= 1024):
+// each wave takes CS_ROWS / 4 rows, four rows' loads in flight at a time, in row order.
+constexpr int CS_ROWS = 64;
+
 __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict__ A, int lda,
                                                         int rows, int cols,
                                                         const float* __restrict__ x,
@@ -95,19 +98,29 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict_
                                                         int ldp) {
     __shared__ float red[4][1024];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int p0 = (blockIdx.x * 4 + w) * 64;
+    const int p0 = blockIdx.x * CS_ROWS + w * (CS_ROWS / 4);
     float acc[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] = 0.0f;
-    const int pend = min(rows, p0 + 64);
-    for (int p = p0; p < pend; ++p) {
-        const float xv = x[(size_t)p * ldx];
-        const float* row = A + (size_t)p * lda;
+    const int pend = min(rows, p0 + CS_ROWS / 4);
+    for (int pb = p0; pb < pend; pb += 4) {
+        float v[4][16], xv[4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int c = lane + 64 * u;
-            if (c < cols) acc[u] = __builtin_fmaf(row[c], xv, acc[u]);
+        for (int q = 0; q < 4; ++q) {
+            const int p = pb + q;
+            const bool ok = p < pend;
+            const float* row = A + (size_t)min(p, pend - 1) * lda;
+            xv[q] = ok ? x[(size_t)min(p, pend - 1) * ldx] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int c = lane + 64 * u;
+                v[q][u] = (ok && c < cols) ? row[c] : 0.0f;
+            }
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc[u] = __builtin_fmaf(v[q][u], xv[q], acc[u]);
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -121,27 +134,49 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict_
 
 void launch_colsum_partial(const float* A, int lda, int rows, int cols, const float* x,
                            int ldx, float* partial, int ldp, hipStream_t st, int* nblk_out) {
-    const int blocks = (rows + 255) / 256;
+    const int blocks = (rows + CS_ROWS - 1) / CS_ROWS;
     *nblk_out = blocks;
     hipLaunchKernelGGL(k_colsum_partial, dim3(blocks), dim3(256), 0, st, A, lda, rows, cols,
                        x, ldx, partial, ldp);
 }
 
+// out[c * ldo] = sum over b < nblk of partial[b, c] (FP64, fixed order): 32 columns per
+// block, 8 row groups of 32 threads with 8 loads in flight each, groups added in order.
 __global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ partial,
                                                       int ldp, int nblk, int cols,
                                                       float* __restrict__ out, int ldo) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= cols) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * ldp + c];
-    out[(size_t)c * ldo] = (float)s;
+    __shared__ double red[8][33];
+    const int cl = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int c = blockIdx.x * 32 + cl;
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    if (c < cols) {
+        int b = grp;
+        for (; b + 56 < nblk; b += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(b + 8 * u) * ldp + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += (double)v[u];
+        }
+        for (; b < nblk; b += 8) a[0] += (double)partial[(size_t)b * ldp + c];
+    }
+    red[grp][cl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    __syncthreads();
+    if (grp == 0 && c < cols) {
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) t += red[g][cl];
+        out[(size_t)c * ldo] = (float)t;
+    }
 }
 
 void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, float* out,
                          int ldo, hipStream_t st) {
     if (cols <= 0) return;
-    hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, partial,
-                       ldp, nblk, cols, out, ldo);
+    hipLaunchKernelGGL(k_colsum_final, dim3((cols + 31) / 32), dim3(256), 0, st, partial, ldp,
+                       nblk, cols, out, ldo);
 }
 
 // ------------------------------------------------------------------------- form_u
