@@ -928,7 +928,13 @@ void launch_round_mot(const float* Mo, const float* S, const ObsDims& d, int j0,
 
 // ----------------------------------------------------------------------- build_block
 // B = [S L^{-T} | S beta | 0] (mp x bp, row-major) for the block product, plus the
-// optional record copies (m rows).  FP64 accumulation.
+// optional record copies (m rows).  FP64 accumulation in the order l = 0, 1, ...  A block
+// stages BB_ROWS rows of S in LDS; thread c computes column c of them, so each load of
+// (L^{-1})[c][l] = LinvT[l][c] (consecutive threads, consecutive words) feeds BB_ROWS
+// products.
+constexpr int BB_ROWS = 16;
+constexpr int BB_MAXI = 256;      // max_actions
+
 __global__ __launch_bounds__(256) void k_build_block(const float* __restrict__ S,
                                                      const double* __restrict__ LinvT,
                                                      const double* __restrict__ beta,
@@ -938,31 +944,45 @@ __global__ __launch_bounds__(256) void k_build_block(const float* __restrict__ S
                                                      float* __restrict__ rec_w,
                                                      float* __restrict__ rec_S,
                                                      const LoopState* __restrict__ ls) {
+    __shared__ float Ss[BB_ROWS][BB_MAXI];
     const int kept = ls->i_eff;
-    const size_t total = (size_t)d.mp * bp;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * 256) {
-        const int p = (int)(e / bp), c = (int)(e % bp);
-        const float* Srow = S + (size_t)p * d.imax;
-        double acc = 0.0;
-        if (p < d.m) {
-            if (c < d.imax) {
-                // (L^{-1})[c][l] = LinvT[l][c]: consecutive lanes (columns c) read
-                // consecutive words
-                for (int l = 0; l <= c; ++l)
-                    acc = __builtin_fma((double)Srow[l], LinvT[(size_t)l * d.imax + c], acc);
-            } else if (c == d.imax) {
-                for (int l = 0; l < d.imax; ++l) acc = __builtin_fma((double)Srow[l], beta[l], acc);
+    const int p0 = blockIdx.x * BB_ROWS;
+    const int imax = d.imax;
+    for (int e = threadIdx.x; e < BB_ROWS * imax; e += blockDim.x) {
+        const int r = e / imax, l = e % imax, p = p0 + r;
+        Ss[r][l] = p < d.m ? S[(size_t)p * imax + l] : 0.0f;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < bp; c += blockDim.x) {
+        double acc[BB_ROWS];
+#pragma unroll
+        for (int r = 0; r < BB_ROWS; ++r) acc[r] = 0.0;
+        if (c < imax) {
+            for (int l = 0; l <= c; ++l) {
+                const double lv = LinvT[(size_t)l * imax + c];
+#pragma unroll
+                for (int r = 0; r < BB_ROWS; ++r) acc[r] = __builtin_fma((double)Ss[r][l], lv, acc[r]);
+            }
+        } else if (c == imax) {
+            for (int l = 0; l < imax; ++l) {
+                const double bv = beta[l];
+#pragma unroll
+                for (int r = 0; r < BB_ROWS; ++r) acc[r] = __builtin_fma((double)Ss[r][l], bv, acc[r]);
             }
         }
-        const float v = (float)acc;
-        B[(size_t)p * ldb + c] = v;
-        if (p < d.m) {
-            if (c < d.imax) {
-                if (rec_W) rec_W[(size_t)p * d.imax + c] = v;
-                if (rec_S) rec_S[(size_t)p * d.imax + c] = c < kept ? Srow[c] : 0.0f;
-            } else if (c == d.imax && rec_w) {
-                rec_w[p] = v;
+#pragma unroll
+        for (int r = 0; r < BB_ROWS; ++r) {
+            const int p = p0 + r;
+            if (p >= d.mp) break;
+            const float v = (float)acc[r];
+            B[(size_t)p * ldb + c] = v;
+            if (p < d.m) {
+                if (c < imax) {
+                    if (rec_W) rec_W[(size_t)p * imax + c] = v;
+                    if (rec_S) rec_S[(size_t)p * imax + c] = c < kept ? Ss[r][c] : 0.0f;
+                } else if (c == imax && rec_w) {
+                    rec_w[p] = v;
+                }
             }
         }
     }
@@ -971,8 +991,7 @@ __global__ __launch_bounds__(256) void k_build_block(const float* __restrict__ S
 void launch_build_block(const float* S, const double* LinvT, const double* beta,
                         const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
                         float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st) {
-    const size_t total = (size_t)d.mp * bp;
-    const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+    const int blocks = (d.mp + BB_ROWS - 1) / BB_ROWS;
     hipLaunchKernelGGL(k_build_block, dim3(blocks), dim3(256), 0, st, S, LinvT, beta, d, B, ldb,
                        bp, rec_W, rec_w, rec_S, ls);
 }
