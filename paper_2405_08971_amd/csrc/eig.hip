@@ -220,8 +220,9 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
 // V_r = Q Z_r for the r leading eigenvectors of T: Z holds T's eigenvectors as columns
 // (column-major, ascending eigenvalues), so output column c (descending order) starts as
 // Z's column K - 1 - c; the reflectors are applied last-to-first, z <- z - tau_j v_j
-// (v_j^T z).  Each wave keeps two columns in registers (lane l holds rows l + 64 u); a
-// workgroup stages BT_CHUNK reflectors at a time in LDS for its four waves.  Writes
+// (v_j^T z).  Each wave keeps one column in registers (lane l holds rows l + 64 u), so r
+// waves run at once; a workgroup stages BT_CHUNK reflectors at a time in LDS for its four
+// waves, the next chunk's loads in flight while the current one is applied.  Writes
 // Vr (FP32, row-major K x r) and, if asked, rot (FP64, row-major K x r).
 constexpr int BT_CHUNK = 8;
 
@@ -231,61 +232,63 @@ __global__ __launch_bounds__(256) void k_backtransform(const double* __restrict_
                                                        const double* __restrict__ tau, int K,
                                                        int r, float* __restrict__ Vr,
                                                        double* __restrict__ rot) {
-    __shared__ double vs[BT_CHUNK][64 * U];
+    constexpr int CH = BT_CHUNK * 64 * U;          // doubles of one staged chunk
+    constexpr int PER = (CH + 255) / 256;          // of them loaded per thread
+    __shared__ double vs[BT_CHUNK * 64 * U];
     __shared__ double ts[BT_CHUNK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col0 = (blockIdx.x * 4 + wave) * 2;
-    double z[2][U];
+    const int col = blockIdx.x * 4 + wave;
+    double z[U];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int c = col0 + q;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = lane + 64 * u;
-            z[q][u] = (c < r && k < K) ? Z[(size_t)(K - 1 - c) * K + k] : 0.0;
-        }
+    for (int u = 0; u < U; ++u) {
+        const int k = lane + 64 * u;
+        z[u] = (col < r && k < K) ? Z[(size_t)(K - 1 - col) * K + k] : 0.0;
     }
+    // the chunk of reflectors j0, j0 - 1, .. (v_j[j + 1] = 1, zero above) into registers
+    double pv[PER], pt = 0.0;
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int jj = e / (64 * U), k = e % (64 * U), j = j0 - jj;
+            double v = 0.0;
+            if (e < CH && j >= 0 && k < K && k >= j + 1) v = (k == j + 1) ? 1.0 : Vh[(size_t)j * K + k];
+            pv[i] = v;
+        }
+        pt = (tid < BT_CHUNK && j0 - tid >= 0) ? tau[j0 - tid] : 0.0;
+    };
+    fetch(K - 3);
     for (int j0 = K - 3; j0 >= 0; j0 -= BT_CHUNK) {
         __syncthreads();
-        for (int e = tid; e < BT_CHUNK * 64 * U; e += 256) {
-            const int jj = e / (64 * U), k = e % (64 * U);
-            const int j = j0 - jj;
-            double v = 0.0;
-            if (j >= 0 && k < K && k >= j + 1) v = (k == j + 1) ? 1.0 : Vh[(size_t)j * K + k];
-            vs[jj][k] = v;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < CH) vs[e] = pv[i];
         }
-        if (tid < BT_CHUNK) ts[tid] = (j0 - tid >= 0) ? tau[j0 - tid] : 0.0;
+        if (tid < BT_CHUNK) ts[tid] = pt;
         __syncthreads();
+        if (j0 - BT_CHUNK >= 0) fetch(j0 - BT_CHUNK);      // in flight during the products
         const int njj = min(BT_CHUNK, j0 + 1);
         for (int jj = 0; jj < njj; ++jj) {
             const double t = ts[jj];
             double vl[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) vl[u] = vs[jj][lane + 64 * u];
-            double d0 = 0.0, d1 = 0.0;
+            for (int u = 0; u < U; ++u) vl[u] = vs[jj * 64 * U + lane + 64 * u];
+            double d0 = 0.0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                d0 = __builtin_fma(vl[u], z[0][u], d0);
-                d1 = __builtin_fma(vl[u], z[1][u], d1);
-            }
-            const double f0 = t * wave_sum(d0), f1 = t * wave_sum(d1);
+            for (int u = 0; u < U; ++u) d0 = __builtin_fma(vl[u], z[u], d0);
+            const double f0 = t * wave_sum(d0);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                z[0][u] = __builtin_fma(-f0, vl[u], z[0][u]);
-                z[1][u] = __builtin_fma(-f1, vl[u], z[1][u]);
-            }
+            for (int u = 0; u < U; ++u) z[u] = __builtin_fma(-f0, vl[u], z[u]);
         }
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int c = col0 + q;
-        if (c >= r) continue;
+    if (col < r) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = lane + 64 * u;
             if (k < K) {
-                Vr[(size_t)k * r + c] = (float)z[q][u];
-                if (rot) rot[(size_t)k * r + c] = z[q][u];
+                Vr[(size_t)k * r + col] = (float)z[u];
+                if (rot) rot[(size_t)k * r + col] = z[u];
             }
         }
     }
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(256) void k_backtransform(const double* __restrict_
 
 void launch_backtransform(const double* Z, const double* Vh, const double* tau, int K, int r,
                           float* Vr, double* rot, hipStream_t st) {
-    const int blocks = (r + 7) / 8;
+    const int blocks = (r + 3) / 4;
     const int u = (K + 63) / 64;
 #define CAKF_BT(N)                                                                          \
     hipLaunchKernelGGL(k_backtransform<N>, dim3(blocks), dim3(256), 0, st, Z, Vh, tau, K, r, \
