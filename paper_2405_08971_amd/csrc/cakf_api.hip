@@ -110,6 +110,7 @@ struct cakf_ctx {
     int gspart_blocks;
     float *gQb, *gMob, *gZr, *gCc;
     double *gW64, *gSr64, *gBb64, *gG1, *gG2, *gX1, *gX2, *gpart, *gacc;
+    double* gatb;      // slab partials of the FP64 products G1, G2
     // path sampler (allocated when cfg.sample_paths > 0)
     int sp_ns, bsp;
     float *sp_B, *sp_W, *sp_Y, *sp_D, *sp_D2, *sp_R, *sp_Z, *sp_Q;
@@ -202,7 +203,7 @@ static void free_all(cakf_ctx* c) {
                     c->sm_WR, c->sm_Bth, c->sm_Btl, c->gMb[0], c->gMb[1], c->gmb, c->gYb,
                     c->gBq, c->gBb, c->gbpart, c->gspart, c->gQb, c->gMob, c->gZr, c->gCc,
                     c->gW64, c->gSr64, c->gBb64, c->gG1, c->gG2, c->gX1, c->gX2, c->gpart,
-                    c->gacc, c->bpart64, c->bpart32, c->bG, c->bpart, c->sp_B,
+                    c->gacc, c->gatb, c->bpart64, c->bpart32, c->bG, c->bpart, c->sp_B,
                     c->sp_W, c->sp_Y, c->sp_D, c->sp_D2, c->sp_R, c->sp_Z, c->sp_Q, c->sp_Bth,
                     c->sp_Btl, c->sp_Xo};
     for (void* p : ptrs)
@@ -389,6 +390,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         rc |= dalloc(&c->gX2, I * I);
         rc |= dalloc(&c->gpart, (n + 3) / 4);
         rc |= dalloc(&c->gacc, 4);
+        rc |= dalloc(&c->gatb, atb64_part_elems(c->mmax, I, I1));
     }
     {
         // Block products with few row blocks are split along the observation axis (see
@@ -555,14 +557,6 @@ static rocblas_status sgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N,
                                float alpha, const float* A, int lda, const float* B, int ldb,
                                float beta, float* C, int ldc) {
     return rocblas_sgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
-                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
-                         &alpha, B, ldb, A, lda, &beta, C, ldc);
-}
-
-static rocblas_status dgemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K,
-                               double alpha, const double* A, int lda, const double* B,
-                               int ldb, double beta, double* C, int ldc) {
-    return rocblas_dgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
                          ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K,
                          &alpha, B, ldb, A, lda, &beta, C, ldc);
 }
@@ -878,10 +872,9 @@ extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, 
             }
             // 4. the Cholesky form in FP64: G1 = W^T Bbar, G2 = S^T [S r0]
             launch_to_f64(c->gBb, bp, m, I1, c->gBb64, I1, st);
-            BLAS_TRY(dgemm_rm(c->blas, true, false, imax, I1, m, 1.0, c->gW64, imax, c->gBb64,
-                              I1, 0.0, c->gG1, I1));
-            BLAS_TRY(dgemm_rm(c->blas, true, false, imax, I1, m, 1.0, c->gSr64, I1, c->gSr64,
-                              I1, 0.0, c->gG2, I1));
+            // (slab products: the library's GEMM does not split the m-long inner dimension)
+            launch_atb64(c->gW64, imax, c->gBb64, I1, m, imax, I1, c->gatb, c->gG1, I1, st);
+            launch_atb64(c->gSr64, I1, c->gSr64, I1, m, imax, I1, c->gatb, c->gG2, I1, st);
             launch_adj_small(J, imax, c->gG1, c->gG2, t.chol, t.chol_inv, c->gX1, c->gX2,
                              c->gCc, c->gacc, 3, st);
             // 5. [Z rbar0] = S [Cbar cbar]; the kernel terms of C = S^T Ghat S

@@ -67,6 +67,12 @@ void launch_block_residual(const float* U, const float* V, float* S, const float
                            const LoopState* ls, hipStream_t st);
 // skinny products of a block-policy round (partial buffer: round_products_elems)
 size_t round_products_elems(int m, int P, int Q);
+// G (P x Q, ld ldg, FP64) = A^T B over m rows, A (m x P, ld lda) and B (m x Q, ld ldb)
+// row-major FP64: slab partial products (part: atb64_part_elems doubles) summed in a fixed
+// order.
+size_t atb64_part_elems(int m, int P, int Q);
+void launch_atb64(const double* A, int lda, const double* B, int ldb, int m, int P, int Q,
+                  double* part, double* G, int ldg, hipStream_t st);
 void launch_round_gram(const float* U, const float* V, const float* S, const float* r0,
                        const ObsDims& d, int j0, int bt, double* part, double* G, int ldg,
                        hipStream_t st);

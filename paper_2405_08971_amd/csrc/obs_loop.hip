@@ -777,6 +777,11 @@ struct RowsA {
     int ld;
     __device__ float operator()(int p, int c) const { return A[(size_t)p * ld + c]; }
 };
+struct RowsA64 {
+    const double* A;
+    int ld;
+    __device__ double operator()(int p, int c) const { return A[(size_t)p * ld + c]; }
+};
 struct RoundGramB {
     const float *U, *S, *V, *r0;
     int ld, j0, bt, lowrank;
@@ -797,28 +802,32 @@ __device__ __forceinline__ double fma_acc(double a, double b, double c) {
 }
 
 // QC columns of B per workgroup (16, 32 or 64; the smallest that holds Q, else 64 and
-// more workgroups along z): thread (cl, qg) accumulates C[c0 + cl, q0 + qg + 4 k].
+// more workgroups along z): thread (cl, qg) accumulates C[c0 + cl, q0 + qg + 4 k].  The
+// operands are staged in the type the loaders return (FP32, or FP64 for FP64 sources).
 template <typename Acc, int QC, class LA, class LB>
 __global__ __launch_bounds__(256) void k_atb_partial(LA la, LB lb, int m, int P, int Q,
                                                      Acc* __restrict__ part) {
+    using TA = decltype(la(0, 0));
+    using TB = decltype(lb(0, 0));
     constexpr int BLD = ATB_RB * QC / 256;      // elements of B each thread loads
-    __shared__ float As[ATB_RB][ATB_PC + 1];
-    __shared__ float Bs[ATB_RB][QC + 1];
+    __shared__ TA As[ATB_RB][ATB_PC + 1];
+    __shared__ TB Bs[ATB_RB][QC + 1];
     const int tid = threadIdx.x;
     const int c0 = blockIdx.y * ATB_PC, q0 = blockIdx.z * QC;
     const int p0 = blockIdx.x * ATB_RB;
     const int cl = tid & 63, qg = tid >> 6;
     // all of the slab's loads are issued before any of them is used
-    float av[ATB_LD], bv[BLD];
+    TA av[ATB_LD];
+    TB bv[BLD];
 #pragma unroll
     for (int u = 0; u < ATB_LD; ++u) {
         const int p = p0 + u * 4 + qg;
-        av[u] = (p < m && c0 + cl < P) ? la(p, c0 + cl) : 0.0f;
+        av[u] = (p < m && c0 + cl < P) ? la(p, c0 + cl) : TA(0);
     }
 #pragma unroll
     for (int u = 0; u < BLD; ++u) {
         const int e = u * 256 + tid, r = e / QC, q = e % QC, p = p0 + r;
-        bv[u] = (p < m && q0 + q < Q) ? lb(p, q0 + q) : 0.0f;
+        bv[u] = (p < m && q0 + q < Q) ? lb(p, q0 + q) : TB(0);
     }
 #pragma unroll
     for (int u = 0; u < ATB_LD; ++u) As[u * 4 + qg][cl] = av[u];
@@ -911,6 +920,20 @@ void launch_round_gram(const float* U, const float* V, const float* S, const flo
     launch_atb_partial<double>(RowsA{S, d.imax},
                                RoundGramB{U, S, V, r0, d.imax, j0, bt, d.rank > 0 ? 1 : 0}, d.m,
                                P, Q, part, st);
+    const int blocks = (P * Q + 63) / 64;
+    hipLaunchKernelGGL((k_atb_reduce<double, false>), dim3(blocks), dim3(256), 0, st, part,
+                       nslab, P, Q, G, ldg, nullptr, 0, 0);
+}
+
+size_t atb64_part_elems(int m, int P, int Q) {
+    return (size_t)((m + ATB_RB - 1) / ATB_RB) * P * Q;
+}
+
+void launch_atb64(const double* A, int lda, const double* B, int ldb, int m, int P, int Q,
+                  double* part, double* G, int ldg, hipStream_t st) {
+    if (m <= 0 || P <= 0 || Q <= 0) return;
+    const int nslab = (m + ATB_RB - 1) / ATB_RB;
+    launch_atb_partial<double>(RowsA64{A, lda}, RowsA64{B, ldb}, m, P, Q, part, st);
     const int blocks = (P * Q + 63) / 64;
     hipLaunchKernelGGL((k_atb_reduce<double, false>), dim3(blocks), dim3(256), 0, st, part,
                        nslab, P, Q, G, ldg, nullptr, 0, 0);
