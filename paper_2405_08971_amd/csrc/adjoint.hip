@@ -411,6 +411,25 @@ void launch_to_f32(const double* A, size_t total, float* out, hipStream_t st) {
     hipLaunchKernelGGL(k_to_f32, dim3(blocks), dim3(256), 0, st, A, total, out);
 }
 
+// out[c * rows + r] = A[r * cols + c]: an FP64 row-major rows x cols matrix as its FP32
+// transpose (row-major cols x rows).
+__global__ void k_to_f32_t(const double* __restrict__ A, int rows, int cols,
+                           float* __restrict__ out) {
+    const size_t total = (size_t)rows * cols;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / rows), r = (int)(e % rows);
+        out[e] = (float)A[(size_t)r * cols + c];
+    }
+}
+
+void launch_to_f32_t(const double* A, int rows, int cols, float* out, hipStream_t st) {
+    const size_t total = (size_t)rows * cols;
+    if (!total) return;
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_to_f32_t, dim3(blocks), dim3(256), 0, st, A, rows, cols, out);
+}
+
 // ------------------------------------------------------------------------ k_adj_small
 // One block, FP64: the Cholesky-form adjoint of one update with J kept actions.
 // G1 = W^T [Bbar_W wbar] and G2 = S^T [S r0] (imax x (imax + 1), row-major).

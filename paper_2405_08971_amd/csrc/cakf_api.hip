@@ -821,11 +821,12 @@ extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, 
         float* Mbk = c->gMb[cur];
         if (t.rotation) {
             const int K = t.rank_full;
-            launch_to_f32(t.rotation, (size_t)K * t.rank, c->Vr, st);
+            // V_r^T (t.rank x K, FP32), so that the product has no transposed operand
+            launch_to_f32_t(t.rotation, K, t.rank, c->Vr, st);
             Mbk = c->gMb[1 - cur];
             if (K > 0)
-                BLAS_TRY(sgemm_rm(c->blas, false, true, n, K, t.rank, 1.0f, c->gMb[cur], ldM,
-                                  c->Vr, t.rank, 0.0f, Mbk, ldM));
+                BLAS_TRY(sgemm_rm(c->blas, false, false, n, K, t.rank, 1.0f, c->gMb[cur], ldM,
+                                  c->Vr, K, 0.0f, Mbk, ldM));
             cur = 1 - cur;
         }
         const int J = t.m > 0 ? kept[k] : 0;

@@ -167,6 +167,7 @@ void launch_adj_obs_prep(const float4* Xs, int n, const int32_t* idx, const floa
 void launch_to_f64(const float* A, int lda, int rows, int cols, double* out, int ldo,
                    hipStream_t st);
 void launch_to_f32(const double* A, size_t total, float* out, hipStream_t st);
+void launch_to_f32_t(const double* A, int rows, int cols, float* out, hipStream_t st);
 void launch_adj_small(int J, int imax, const double* G1, const double* G2, const double* L,
                       const double* Linv, double* X1, double* X2, float* Cc, double* grad,
                       int inoise, hipStream_t st);
