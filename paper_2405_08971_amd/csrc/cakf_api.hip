@@ -959,11 +959,13 @@ static int smooth_moments(cakf_ctx* c, const cakf_smooth_input* in, float g, flo
     HIP_TRY(hipMemcpyAsync(c->sm_Z, c->sm_Y, (size_t)c->n * c->bps * sizeof(float),
                            hipMemcpyDeviceToDevice, st));
     if (in->rank > 0) {
-        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                               in->rank, b, c->n, &one, in->factor, in->ld, c->sm_B, c->bps, &zero,
-                               c->sm_Q, c->Kmax));
-        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, b,
-                               c->n, in->rank, &mg2, c->sm_Q, c->Kmax, in->factor, in->ld, &one,
+        // Q^T = Bs^T M (b x rank, column-major ld bps), then Z^T -= g^2 Q^T M^T: neither
+        // product has a transposed operand on the long side
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, b,
+                               in->rank, c->n, &one, c->sm_B, c->bps, in->factor, in->ld, &zero,
+                               c->sm_Q, c->bps));
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_none, b, c->n,
+                               in->rank, &mg2, c->sm_Q, c->bps, in->factor, in->ld, &one,
                                c->sm_Z, c->bps));
     }
     launch_smooth_out(in->mean, in->factor, in->ld, in->rank, g, c->sm_Z, c->bps, b, c->n,
@@ -991,19 +993,20 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
                                hipMemcpyDeviceToDevice, st));
         if (in->pred_rank > 0) {
             BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                                   in->pred_rank, b, c->n, &one, in->pred_factor, in->pred_ld,
-                                   c->sm_B, c->bps, &zero, c->sm_Q, c->Kmax));
-            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none,
-                                   b, c->n, in->pred_rank, &mone, c->sm_Q, c->Kmax,
-                                   in->pred_factor, in->pred_ld, &one, c->sm_Z, c->bps));
+                                   b, in->pred_rank, c->n, &one, c->sm_B, c->bps,
+                                   in->pred_factor, in->pred_ld, &zero, c->sm_Q, c->bps));
+            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_none, b,
+                                   c->n, in->pred_rank, &mone, c->sm_Q, c->bps, in->pred_factor,
+                                   in->pred_ld, &one, c->sm_Z, c->bps));
         }
-        // R = W_obs^T Pm[idx, :] (imax x b), WR = W_obs R (m x b)
+        // R = W_obs^T Pm[idx, :] (imax x b), WR = W_obs R (m x b); R is kept as R^T
+        // (b x imax, column-major ld bps) so that WR^T = R^T W_obs^T needs no transpose
         launch_gather_rows(c->sm_Z, c->bps, in->idx, in->m, c->n, b, c->sm_Gr, c->bps, st);
-        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                               c->imax, b, in->m, &one, in->W_obs, c->imax, c->sm_Gr, c->bps, &zero,
-                               c->sm_R, c->imax));
-        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, b,
-                               in->m, c->imax, &one, c->sm_R, c->imax, in->W_obs, c->imax, &zero,
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, b,
+                               c->imax, in->m, &one, c->sm_Gr, c->bps, in->W_obs, c->imax, &zero,
+                               c->sm_R, c->bps));
+        BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_none, b, in->m,
+                               c->imax, &one, c->sm_R, c->bps, in->W_obs, c->imax, &zero,
                                c->sm_WR, c->bps));
     }
     // ws = w + proj[:, 0], [W, proj[:, 1:]] with proj = Bs - H^T (W_obs R)
