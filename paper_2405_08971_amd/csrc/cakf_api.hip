@@ -696,8 +696,8 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     if (d.rank > 0) {
         const float one = 1.0f, zero = 0.0f;
         // Q^T = B^T Mo  (b x rank, column-major ld bp), so that the product with the factor
-        // below needs no transposed operand (the library's kernel for that form is ~2.5x
-        // faster at these shapes)
+        // below needs no transposed operand (the library's kernel for that form is about
+        // twice as fast at these shapes)
         BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, b,
                                d.rank, m, &one, c->B, c->bp, c->Mo, c->ldmo, &zero, c->Q, c->bp));
     }
