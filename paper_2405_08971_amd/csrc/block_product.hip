@@ -6,139 +6,6 @@
 
 namespace cakf {
 
-// ------------------------------------------------------------------- FP32 (VALU) form
-// Block: 64 state rows x 16 CPT columns (CPT <= 10); the observation axis is walked in
-// chunks of 64.  Each chunk: the 64 x 64 kernel tile is evaluated once into LDS (4 rows x
-// 4 observations per thread, stored observation-major so that a thread's 4 rows are one
-// 16-byte read), then thread (rg, cg) = (tid % 16, tid / 16) accumulates rows
-// 4 rg .. 4 rg + 3 against columns cg CPT .. cg CPT + CPT - 1: per observation one kernel
-// read and ceil(CPT / 4) B reads (16 bytes each) feed 4 CPT FMAs.
-constexpr int BP_ROWS = 64;
-constexpr int BP_CHUNK = 64;
-constexpr int BP_CG = 16;
-constexpr int BP_MAXCPT = 10;
-constexpr int BP_COLS = BP_CG * BP_MAXCPT;
-
-template <int NU2, int DIST, int CPT>
-__global__ __launch_bounds__(256) void k_block_fp32(const float4* __restrict__ Xs, int n,
-                                                    const float4* __restrict__ Xo, int m,
-                                                    const float* __restrict__ B, int ldb,
-                                                    int col0, int ncols, float sigma_f2,
-                                                    float* __restrict__ out, int ldo,
-                                                    int qchunk, size_t part_stride) {
-    constexpr int C4 = (CPT + 3) / 4;                  // 16-byte B reads per observation
-    constexpr int BCOLS = BP_CG * CPT;
-    __shared__ float4 xo[BP_CHUNK];
-    __shared__ float4 Bs[BP_CHUNK][BP_CG][C4];         // [q][cg][c / 4]
-    __shared__ float4 Kt[BP_CHUNK][BP_ROWS / 4 + 1];   // [q][rg] = K(rows 4 rg .. 4 rg + 3, q)
-    const int tid = threadIdx.x;
-    const int rg = tid & 15, cg = tid >> 4;
-    const int row0 = blockIdx.x * BP_ROWS;
-    float4 xr[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) xr[i] = prep_row<DIST>(Xs[min(row0 + 4 * rg + i, n - 1)]);
-    float acc[4][CPT];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) acc[i][c] = 0.0f;
-
-    // observation range of this split: [blockIdx.y qchunk, min(m, (blockIdx.y + 1) qchunk))
-    const int qend = min(m, (int)(blockIdx.y + 1) * qchunk);
-    out += blockIdx.y * part_stride;
-    for (int q0 = blockIdx.y * qchunk; q0 < qend; q0 += BP_CHUNK) {
-        const int qn = min(BP_CHUNK, qend - q0);
-        __syncthreads();
-        if (tid < BP_CHUNK) xo[tid] = Xo[q0 + min(tid, qn - 1)];
-        // B chunk, filled in LDS order: 16-byte slot (q, g, k4) holds columns
-        // g CPT + 4 k4 .. + 3 of row q (zero beyond the group's CPT columns, ncols and qn).
-        // Loads are clamped into the chunk instead of branched around; all of a thread's
-        // loads are issued before the first store.
-        constexpr int SLOTS = BP_CHUNK * BP_CG * C4 / 256;
-        float4 bv[SLOTS];
-#pragma unroll
-        for (int u = 0; u < SLOTS; ++u) {
-            const int sl = tid + 256 * u;
-            const int q = sl / (BP_CG * C4), g = (sl / C4) % BP_CG, k4 = sl % C4;
-            const float* src = B + (size_t)(q0 + min(q, qn - 1)) * ldb + col0;
-            float v[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int cc = 4 * k4 + t, c = g * CPT + cc;
-                const bool ok = q < qn && cc < CPT && c < ncols;
-                const float x = src[min(c, ncols - 1)];
-                v[t] = ok ? x : 0.0f;
-            }
-            bv[u] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-#pragma unroll
-        for (int u = 0; u < SLOTS; ++u) (&Bs[0][0][0])[tid + 256 * u] = bv[u];
-        __syncthreads();
-        // kernel tile: rows 4 rg .. 4 rg + 3, observations 4 cg .. 4 cg + 3
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float4 b = xo[4 * cg + u];
-            Kt[4 * cg + u][rg] = make_float4(kval<NU2, DIST>(xr[0], b), kval<NU2, DIST>(xr[1], b),
-                                             kval<NU2, DIST>(xr[2], b), kval<NU2, DIST>(xr[3], b));
-        }
-        __syncthreads();
-        for (int q = 0; q < qn; ++q) {
-            const float4 k4 = Kt[q][rg];
-            float bq[4 * C4];
-#pragma unroll
-            for (int c4 = 0; c4 < C4; ++c4) {
-                const float4 b = Bs[q][cg][c4];
-                bq[4 * c4 + 0] = b.x;
-                bq[4 * c4 + 1] = b.y;
-                bq[4 * c4 + 2] = b.z;
-                bq[4 * c4 + 3] = b.w;
-            }
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                acc[0][c] = __builtin_fmaf(k4.x, bq[c], acc[0][c]);
-                acc[1][c] = __builtin_fmaf(k4.y, bq[c], acc[1][c]);
-                acc[2][c] = __builtin_fmaf(k4.z, bq[c], acc[2][c]);
-                acc[3][c] = __builtin_fmaf(k4.w, bq[c], acc[3][c]);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int p = row0 + 4 * rg + i;
-        if (p < n) {
-            float* orow = out + (size_t)p * ldo + col0;
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int col = cg * CPT + c;
-                if (col < ncols) orow[col] = sigma_f2 * acc[i][c];
-            }
-        }
-    }
-}
-
-template <int NU2, int DIST>
-static void launch_fp32_cols(int cpt, dim3 grid, hipStream_t st, const float4* Xs, int n,
-                             const float4* Xo, int m, const float* B, int ldb, int col0,
-                             int ncols, float sigma_f2, float* out, int ldo, int qchunk,
-                             size_t part_stride) {
-#define CAKF_BP(CPTV)                                                                        \
-    hipLaunchKernelGGL((k_block_fp32<NU2, DIST, CPTV>), grid, dim3(256), 0, st, Xs, n, Xo, m, \
-                       B, ldb, col0, ncols, sigma_f2, out, ldo, qchunk, part_stride)
-    switch (cpt) {
-        case 1: CAKF_BP(1); break;
-        case 2: CAKF_BP(2); break;
-        case 3: CAKF_BP(3); break;
-        case 4: CAKF_BP(4); break;
-        case 5: CAKF_BP(5); break;
-        case 6: CAKF_BP(6); break;
-        case 7: CAKF_BP(7); break;
-        case 8: CAKF_BP(8); break;
-        case 9: CAKF_BP(9); break;
-        default: CAKF_BP(10); break;
-    }
-#undef CAKF_BP
-}
-
 // ------------------------------------------------------------------- BF16 MFMA form
 // v_mfma_f32_32x32x16_bf16 (D = A B, A 32 x 16, B 16 x 32): lane l supplies
 // A[l % 32][8 (l / 32) + t] and B[8 (l / 32) + t][l % 32], t = 0..7, and holds
@@ -286,6 +153,88 @@ static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const 
 #undef CAKF_MF
 }
 
+// FP32 MFMA form of the same product (v_mfma_f32_32x32x2f32, full FP32 operands and
+// accumulation): lane l supplies A[l % 32][l / 32] = K(row l % 32, observation l / 32 of
+// the k-step), evaluated on the VALU, and B[l / 32][l % 32] from the LDS chunk, and
+// holds D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32] in register i.  Each wave owns 32 state
+// rows and NT 32-column tiles; a workgroup's four waves share the chunk of 64
+// observations of B.
+constexpr int F32_KC = 64;
+template <int NU2, int DIST, int NT>
+__global__ __launch_bounds__(256) void k_block_mfma32(const float4* __restrict__ Xs, int n,
+                                                      const float4* __restrict__ Xo, int m,
+                                                      const float* __restrict__ B, int ldb,
+                                                      int col0, int ncols, float sigma_f2,
+                                                      float* __restrict__ out, int ldo,
+                                                      int qchunk, size_t part_stride) {
+    constexpr int BC = NT * 32;
+    constexpr int BLD = F32_KC * BC / 256;          // B elements each thread stages
+    __shared__ float4 xo[F32_KC];
+    __shared__ float Bs[F32_KC][BC];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int rl = lane & 31, half = lane >> 5;
+    const int row0 = blockIdx.x * MF_ROWS + w * 32;
+    const float4 xa = prep_row<DIST>(Xs[min(row0 + rl, n - 1)]);
+    f32x16 acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[c][i] = 0.0f;
+    const int qend = min(m, (int)(blockIdx.y + 1) * qchunk);
+    out += blockIdx.y * part_stride;
+    for (int q0 = blockIdx.y * qchunk; q0 < qend; q0 += F32_KC) {
+        const int qn = min(F32_KC, qend - q0);
+        __syncthreads();
+        if (tid < F32_KC) xo[tid] = Xo[q0 + min(tid, qn - 1)];
+        float bv[BLD];
+#pragma unroll
+        for (int u = 0; u < BLD; ++u) {
+            const int e = tid + 256 * u, q = e / BC, c = e % BC;
+            const float x = B[(size_t)(q0 + min(q, qn - 1)) * ldb + col0 + min(c, ncols - 1)];
+            bv[u] = (q < qn && c < ncols) ? x : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < BLD; ++u) (&Bs[0][0])[tid + 256 * u] = bv[u];
+        __syncthreads();
+#pragma unroll 4
+        for (int ks = 0; ks < F32_KC / 2; ++ks) {
+            const int k = 2 * ks + half;
+            const float a = kval<NU2, DIST>(xa, xo[k]);
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Bs[k][32 * c + rl], acc[c], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const int col = 32 * c + rl;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = row0 + 8 * (i / 4) + 4 * half + (i % 4);
+            if (row < n && col < ncols) out[(size_t)row * ldo + col0 + col] = sigma_f2 * acc[c][i];
+        }
+    }
+}
+
+template <int NU2, int DIST>
+static void launch_mfma32_tiles(int nt, dim3 grid, hipStream_t st, const float4* Xs, int n,
+                                const float4* Xo, int m, const float* B, int ldb, int col0,
+                                int ncols, float sigma_f2, float* out, int ldo, int qchunk,
+                                size_t part_stride) {
+#define CAKF_F32(NTV)                                                                        \
+    hipLaunchKernelGGL((k_block_mfma32<NU2, DIST, NTV>), grid, dim3(256), 0, st, Xs, n, Xo, m, \
+                       B, ldb, col0, ncols, sigma_f2, out, ldo, qchunk, part_stride)
+    switch (nt) {
+        case 1: CAKF_F32(1); break;
+        case 2: CAKF_F32(2); break;
+        case 3: CAKF_F32(3); break;
+        case 4: CAKF_F32(4); break;
+        default: CAKF_F32(5); break;
+    }
+#undef CAKF_F32
+}
+
 // Split B (FP32, row-major mp x ldb, columns 0..bp) into transposed BF16 parts:
 // Bth[c * mp + q] = bf16(B[o, c]), Btl = bf16(B - Bth), o = q or, with perm, md_perm(q).
 __global__ void k_split_bt(const float* __restrict__ B, int mp, int ldb, int bcols, int bp,
@@ -341,14 +290,14 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
     const int ldd = nsplit > 1 ? bcols : ldo;
     const size_t stride = nsplit > 1 ? (size_t)n * bcols : 0;
     if (prec == 0) {
-        const int blocks = (n + BP_ROWS - 1) / BP_ROWS;
-        for (int c0 = 0; c0 < bcols; c0 += BP_COLS) {
-            const int nc = std::min(BP_COLS, bcols - c0);
-            const int cpt = (nc + BP_CG - 1) / BP_CG;      // columns per thread, 1 .. 10
+        const int blocks = (n + MF_ROWS - 1) / MF_ROWS;
+        for (int c0 = 0; c0 < bcols; c0 += 160) {
+            const int nc = std::min(160, bcols - c0);
+            const int nt = (nc + 31) / 32;
             CAKF_DISPATCH_KERNEL(nu2, dist,
-                (launch_fp32_cols<NU2, DIST>(cpt, dim3(blocks, nsplit), st, Xs, n, Xo, m, B, ldb,
-                                             c0, nc, sigma_f2, dst + c0, ldd,
-                                             nsplit > 1 ? qchunk : m, stride)));
+                (launch_mfma32_tiles<NU2, DIST>(nt, dim3(blocks, nsplit), st, Xs, n, Xo, m, B,
+                                                ldb, c0, nc, sigma_f2, dst, ldd,
+                                                nsplit > 1 ? qchunk : m, stride)));
         }
     } else {
         const int ntiles = (bcols + 31) / 32;
