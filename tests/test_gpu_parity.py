@@ -51,6 +51,18 @@ def test_given_actions_fp32_matches_oracle(case):
     _check(compare(cfg, model, recs, gpu, probes), FP32_TOL)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("bf16x3", 1e-4)])
+def test_more_than_160_block_columns(prec, tol):
+    """i + 1 = 171 columns of [W w]: the block product runs two column blocks (160 + 11)."""
+    cfg = small_config("wide", dim=2, nu2=3, ell=0.25, n=800, m=600, i=170, r=20, T=2,
+                       noise_var=0.3)
+    X, steps, actions = inputs(cfg, seed=12)
+    model, recs = oracle_run(cfg, X, steps, actions, "given")
+    probes = np.random.default_rng(3).standard_normal((cfg.n, 3))
+    gpu = gpu_run(cfg, X, steps, actions, "given", prec, probes=probes)
+    _check(compare(cfg, model, recs, gpu, probes), tol)
+
+
 def test_cg_fp32_matches_oracle_end_to_end():
     cfg = small_config("cg", n=700, m=220, i=6, r=15, T=5)
     X, steps, _ = inputs(cfg, seed=2, policy="cg")
