@@ -1,5 +1,6 @@
 """Full-size checks in the benchmark's launch configuration (n = 65536 sphere points,
-Matern-5/2, m = 16384, i = 128 CG actions, r = 512, BF16X3 block product).
+Matern-5/2, m = 16384, i = 128 CG actions, r = 512), with the BF16X3 block product and
+with the FP32 one.
 
 The FP64 oracle cannot run whole steps at this size, so the GPU's outputs are checked
 against properties that hold at any size, each evaluated in FP64 with the oracle's
@@ -48,7 +49,8 @@ def check_truncation(M, Mplus, r):
     assert e_val < 1e-5 and e_off < 1e-5 and abs(kept - 1.0) < 1e-6
 
 
-def test_full_size_step_properties():
+@pytest.mark.parametrize("prec,tol_bp", [("bf16x3", 1e-3), ("fp32", 1e-4)])
+def test_full_size_step_properties(prec, tol_bp):
     import torch
     from paper_2405_08971_amd.filter import CAKF, Record
 
@@ -58,7 +60,7 @@ def test_full_size_step_properties():
     X64 = X32.astype(np.float64)
     f = CAKF(torch.from_numpy(X32).cuda(), nu2=cfg.nu2, lengthscale=cfg.ell,
              signal_var=cfg.sigma_f2, noise_var=cfg.noise_var, ou_coeff=cfg.a,
-             max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy="cg", prec="bf16x3")
+             max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy="cg", prec=prec)
     rng = np.random.default_rng(0)
     check_steps = (1, 6)
     for k in range(1, 7):
@@ -114,7 +116,7 @@ def test_full_size_step_properties():
                                mean.cpu().numpy()[rows] - mean_pred.cpu().numpy()[rows]])
         e = _rel(got, ref)
         print(f"  block product rel err on sampled rows {e:.2e}", flush=True)
-        assert e < 1e-3
+        assert e < tol_bp
         f.truncate()
         if M.shape[1] > cfg.r:
             check_truncation(M, f.state()[1], cfg.r)
