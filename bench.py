@@ -45,7 +45,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--config", default="c3")
+    p.add_argument("--config", default="sphere_n65536")
     p.add_argument("--prec", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
     p.add_argument("--no-fp32-compare", action="store_true",
                    help="skip the FP32-plain run reported next to the headline mode")
@@ -189,7 +189,7 @@ def next_rows(seed=0):
     from paper_2405_08971_amd.workload import CONFIGS, Workload
 
     out = {}
-    cfg = CONFIGS["c4"]
+    cfg = CONFIGS["sphere_n16384"]
     wl = Workload(cfg, seed=seed)
     X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
     steps = device_inputs(wl, range(1, cfg.T + 1))
@@ -214,7 +214,7 @@ def next_rows(seed=0):
     del ll
     torch.cuda.empty_cache()
 
-    cfg = CONFIGS["c2"]
+    cfg = CONFIGS["sphere_gc_n16384"]
     wl = Workload(cfg, seed=seed)
     X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
     steps = device_inputs(wl, range(1, cfg.T + 1))

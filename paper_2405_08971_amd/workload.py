@@ -75,16 +75,21 @@ class Config:
 # The five workloads of the hot path (small planar case, the FP32 sphere case, the
 # n = 65536 precision case, the differentiation case and the large case).
 CONFIGS = {
-    "c1": Config("c1", n=1024, dim=2, nu2=3, ell=0.2, sigma_f2=1.0, dt=1.0, ell_t=5.0,
-                 T=20, m=256, noise_var=0.01, i=16, r=64),
-    "c2": Config("c2", n=16384, dim=3, nu2=3, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
-                 T=100, m=4096, noise_var=0.05, i=64, r=256, dist=1),
-    "c3": Config("c3", n=65536, dim=3, nu2=5, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
-                 T=200, m=16384, noise_var=0.05, i=128, r=512),
-    "c4": Config("c4", n=16384, dim=3, nu2=3, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
-                 T=50, m=4096, noise_var=0.05, i=64, r=256),
-    "c5": Config("c5", n=262144, dim=3, nu2=3, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
-                 T=50, m=32768, noise_var=0.02, i=256, r=1024, missing_frac=0.1),
+    "plane_n1024": Config(
+        "plane_n1024", n=1024, dim=2, nu2=3, ell=0.2, sigma_f2=1.0, dt=1.0, ell_t=5.0,
+        T=20, m=256, noise_var=0.01, i=16, r=64),
+    "sphere_gc_n16384": Config(
+        "sphere_gc_n16384", n=16384, dim=3, nu2=3, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
+        T=100, m=4096, noise_var=0.05, i=64, r=256, dist=1),
+    "sphere_n65536": Config(
+        "sphere_n65536", n=65536, dim=3, nu2=5, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
+        T=200, m=16384, noise_var=0.05, i=128, r=512),
+    "sphere_n16384": Config(
+        "sphere_n16384", n=16384, dim=3, nu2=3, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
+        T=50, m=4096, noise_var=0.05, i=64, r=256),
+    "sphere_n262144": Config(
+        "sphere_n262144", n=262144, dim=3, nu2=3, ell=0.3, sigma_f2=1.0, dt=1.0, ell_t=5.0,
+        T=50, m=32768, noise_var=0.02, i=256, r=1024, missing_frac=0.1),
 }
 
 

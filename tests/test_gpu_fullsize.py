@@ -54,7 +54,7 @@ def test_full_size_step_properties(prec, tol_bp):
     import torch
     from paper_2405_08971_amd.filter import CAKF, Record
 
-    cfg = CONFIGS["c3"]
+    cfg = CONFIGS["sphere_n65536"]
     wl = Workload(cfg, seed=0)
     X32 = wl.X.astype(np.float32)
     X64 = X32.astype(np.float64)

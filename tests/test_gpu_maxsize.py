@@ -18,7 +18,7 @@ def test_max_size_step_properties():
     import torch
     from paper_2405_08971_amd.filter import CAKF, Record
 
-    cfg = CONFIGS["c5"]
+    cfg = CONFIGS["sphere_n262144"]
     wl = Workload(cfg, seed=0)
     X32 = wl.X.astype(np.float32)
     X64 = X32.astype(np.float64)
