@@ -6,28 +6,11 @@ of Sec. 2 with a Matern-1/2 prior and an Ornstein-Uhlenbeck transition); with on
 observation per step the computation-aware filter is exact (Prop. A.2), and so is its
 smoother (Alg. 3), whose step-1 moments the fixture gives by the Rauch-Tung-Striebel step.
 """
-import math
-import os
-
 import numpy as np
 
 from oracle.caks import run_smoother
 from oracle.cakf import Model, run_filter
-
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "two_point_filter.txt")
-
-
-def _load(path):
-    env = {"e": math.exp(-1.0), "log": math.log, "pi": math.pi}
-    vals = {}
-    with open(path) as fh:
-        for line in fh:
-            line = line.strip()
-            if not line or line.startswith("#"):
-                continue
-            name, expr = (s.strip() for s in line.split("=", 1))
-            vals[name] = eval(expr, {"__builtins__": {}}, {**env, **vals})
-    return vals
+from tiny import load_golden
 
 
 def _problem(g):
@@ -39,7 +22,7 @@ def _problem(g):
 
 
 def test_two_point_filter_matches_the_hand_worked_moments():
-    g = _load(GOLDEN)
+    g = load_golden("two_point_filter.txt")
     model, steps = _problem(g)
     for policy in ("cg", "given"):
         actions = [np.ones((1, 1)), np.full((1, 1), -3.0)] if policy == "given" else None
@@ -53,7 +36,7 @@ def test_two_point_filter_matches_the_hand_worked_moments():
 
 
 def test_two_point_smoother_matches_the_hand_worked_rts_step():
-    g = _load(GOLDEN)
+    g = load_golden("two_point_filter.txt")
     model, steps = _problem(g)
     recs = run_filter(model, steps, 1, 100, policy="cg")
     sm = run_smoother(model, recs, 100)

@@ -1,5 +1,9 @@
-"""Tiny seeded problems for the oracle pin tests (inputs only)."""
+"""Tiny seeded problems for the oracle pin tests (inputs only), and the reader of the
+hand-worked fixtures under golden/."""
 from __future__ import annotations
+
+import math
+import os
 
 import numpy as np
 
@@ -41,3 +45,21 @@ def dense_obs(model, steps, actions=None):
         else:
             out.append((H, R, y))
     return out
+
+
+GOLDEN_DIR = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load_golden(name):
+    """Values of a golden/ fixture: lines "name = expression", evaluated in order with
+    e = exp(-1), log and pi (and the names defined above them) in scope."""
+    env = {"e": math.exp(-1.0), "log": math.log, "pi": math.pi}
+    vals = {}
+    with open(os.path.join(GOLDEN_DIR, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, expr = (t.strip() for t in line.split("=", 1))
+            vals[key] = eval(expr, {"__builtins__": {}}, {**env, **vals})
+    return vals
