@@ -77,12 +77,45 @@ def gram_dell(A, B, nu2, ell, s2=1.0, dist=EUCLID) -> np.ndarray:
     return matern_dell(nu2, distances(A, B, dist), ell, s2)
 
 
-def gram_matmul(A, B, V, nu2, ell, s2=1.0, dist=EUCLID, rows_per_chunk=2048) -> np.ndarray:
+def _threads() -> int:
+    """Worker threads for gram_matmul: ORACLE_THREADS, else every host core."""
+    import os
+    env = os.environ.get("ORACLE_THREADS")
+    if env:
+        return max(1, int(env))
+    return max(1, os.cpu_count() or 1)
+
+
+def gram_matmul(A, B, V, nu2, ell, s2=1.0, dist=EUCLID, rows_per_chunk=512) -> np.ndarray:
     """k(A, B) @ V.  The covariance rows are formed a slab of rows of A at a time only
-    to bound memory: each output row is the plain sum over B."""
+    to bound memory: each output row is the plain sum over B.  Large products spread
+    the slabs over a pool of threads (NumPy releases the interpreter lock inside its
+    array operations); every slab is computed exactly as it would be alone, and the
+    matrix library runs single-threaded inside the pool."""
     V = np.asarray(V, np.float64)
     out = np.empty((A.shape[0],) + V.shape[1:], np.float64)
-    for p0 in range(0, A.shape[0], rows_per_chunk):
-        p1 = min(A.shape[0], p0 + rows_per_chunk)
+    slabs = [(p0, min(A.shape[0], p0 + rows_per_chunk))
+             for p0 in range(0, A.shape[0], rows_per_chunk)]
+
+    def one(sl):
+        p0, p1 = sl
         out[p0:p1] = gram(A[p0:p1], B, nu2, ell, s2, dist) @ V
+
+    nthreads = min(_threads(), len(slabs))
+    if nthreads <= 1 or A.shape[0] * B.shape[0] < (1 << 22):
+        for sl in slabs:
+            one(sl)
+        return out
+    from concurrent.futures import ThreadPoolExecutor
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(1)
+    except Exception:                       # threadpoolctl missing: BLAS keeps its threads
+        limit = None
+    try:
+        with ThreadPoolExecutor(nthreads) as ex:
+            list(ex.map(one, slabs))
+    finally:
+        if limit is not None:
+            limit.restore_original_limits()
     return out

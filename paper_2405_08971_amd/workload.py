@@ -169,8 +169,23 @@ class Workload:
             self._init_prior()
         Xs = self.X if idx is None else self.X[idx]
         w = self._weights(k)
-        feats = np.cos(Xs @ self._omega.T + self._phase)
-        return math.sqrt(self.cfg.sigma_f2 * 2.0 / self.n_features) * (feats @ w)
+        scale = math.sqrt(self.cfg.sigma_f2 * 2.0 / self.n_features)
+        out = np.empty(Xs.shape[0], np.float64)
+
+        def rows(p0, p1):
+            feats = np.cos(Xs[p0:p1] @ self._omega.T + self._phase)
+            out[p0:p1] = scale * (feats @ w)
+
+        chunk = 2048
+        spans = [(p0, min(Xs.shape[0], p0 + chunk)) for p0 in range(0, Xs.shape[0], chunk)]
+        if len(spans) == 1:
+            rows(*spans[0])
+        else:                     # NumPy releases the interpreter lock in cos and matmul
+            from concurrent.futures import ThreadPoolExecutor
+            import os
+            with ThreadPoolExecutor(min(len(spans), os.cpu_count() or 1)) as ex:
+                list(ex.map(lambda sp: rows(*sp), spans))
+        return out
 
     def feature_map(self):
         """(omega, phase, scale) of the random-Fourier-feature surrogate of the spatial
