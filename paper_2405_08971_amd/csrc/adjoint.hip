@@ -52,7 +52,7 @@ __device__ __forceinline__ void matern_and_dlog(float up, float& k, float& kd) {
 
 template <int NU2, int DIST>
 __device__ __forceinline__ float pair_dist(const float4 ap, const float4 b) {
-    if constexpr (NU2 == 1 && DIST == DIST_EUCLID) return scaled_dist_diff(ap, b);
+    if constexpr (DIST == DIST_EUCLID) return scaled_dist_diff(ap, b);
     else return scaled_dist<DIST>(ap, b);
 }
 

@@ -153,13 +153,18 @@ static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const 
 #undef CAKF_MF
 }
 
-// FP32 MFMA form of the same product (v_mfma_f32_32x32x2f32, full FP32 operands and
-// accumulation): lane l supplies A[l % 32][l / 32] = K(row l % 32, observation l / 32 of
-// the k-step), evaluated on the VALU, and B[l / 32][l % 32] from the LDS chunk, and
-// holds D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32] in register i.  Each wave owns 32 state
-// rows and NT 32-column tiles; a workgroup's four waves share the chunk of 64
-// observations of B.
+// FP32 MFMA form of the same product (v_mfma_f32_32x32x2f32, full FP32 operands): lane l
+// supplies A[l % 32][l / 32] = K(row l % 32, observation l / 32 of the k-step), evaluated
+// on the VALU (difference form of the distance), and B[l / 32][l % 32] from the LDS chunk,
+// and holds D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32] in register i.  Each wave owns 32
+// state rows and NT 32-column tiles; a workgroup's four waves share the chunk of 64
+// observations of B.  The MFMA accumulates one chunk in FP32; the chunk sums are added
+// into FP64 accumulators, so the rounding error grows with the chunk length (64) rather
+// than with m: the columns of [W w] are Ghat-orthonormal search directions whose products
+// with the kernel matrix cancel by two to three orders of magnitude, and a plain FP32
+// sum over m = 600 observations already left ~1e-5 in the posterior variance.
 constexpr int F32_KC = 64;
+constexpr int F32_MAXNT = 5;     // column tiles per launch (FP64 accumulators: 32 VGPRs each)
 template <int NU2, int DIST, int NT>
 __global__ __launch_bounds__(256) void k_block_mfma32(const float4* __restrict__ Xs, int n,
                                                       const float4* __restrict__ Xo, int m,
@@ -177,10 +182,11 @@ __global__ __launch_bounds__(256) void k_block_mfma32(const float4* __restrict__
     const int row0 = blockIdx.x * MF_ROWS + w * 32;
     const float4 xa = prep_row<DIST>(Xs[min(row0 + rl, n - 1)]);
     f32x16 acc[NT];
+    double dacc[NT][16];
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[c][i] = 0.0f;
+        for (int i = 0; i < 16; ++i) dacc[c][i] = 0.0;
     const int qend = min(m, (int)(blockIdx.y + 1) * qchunk);
     out += blockIdx.y * part_stride;
     for (int q0 = blockIdx.y * qchunk; q0 < qend; q0 += F32_KC) {
@@ -197,6 +203,10 @@ __global__ __launch_bounds__(256) void k_block_mfma32(const float4* __restrict__
 #pragma unroll
         for (int u = 0; u < BLD; ++u) (&Bs[0][0])[tid + 256 * u] = bv[u];
         __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[c][i] = 0.0f;
 #pragma unroll 4
         for (int ks = 0; ks < F32_KC / 2; ++ks) {
             const int k = 2 * ks + half;
@@ -205,6 +215,10 @@ __global__ __launch_bounds__(256) void k_block_mfma32(const float4* __restrict__
             for (int c = 0; c < NT; ++c)
                 acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Bs[k][32 * c + rl], acc[c], 0, 0, 0);
         }
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) dacc[c][i] += (double)acc[c][i];
     }
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
@@ -212,7 +226,8 @@ __global__ __launch_bounds__(256) void k_block_mfma32(const float4* __restrict__
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int row = row0 + 8 * (i / 4) + 4 * half + (i % 4);
-            if (row < n && col < ncols) out[(size_t)row * ldo + col0 + col] = sigma_f2 * acc[c][i];
+            if (row < n && col < ncols)
+                out[(size_t)row * ldo + col0 + col] = (float)((double)sigma_f2 * dacc[c][i]);
         }
     }
 }
@@ -291,8 +306,8 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
     const size_t stride = nsplit > 1 ? (size_t)n * bcols : 0;
     if (prec == 0) {
         const int blocks = (n + MF_ROWS - 1) / MF_ROWS;
-        for (int c0 = 0; c0 < bcols; c0 += 160) {
-            const int nc = std::min(160, bcols - c0);
+        for (int c0 = 0; c0 < bcols; c0 += 32 * F32_MAXNT) {
+            const int nc = std::min(32 * F32_MAXNT, bcols - c0);
             const int nt = (nc + 31) / 32;
             CAKF_DISPATCH_KERNEL(nu2, dist,
                 (launch_mfma32_tiles<NU2, DIST>(nt, dim3(blocks, nsplit), st, Xs, n, Xo, m, B,

@@ -11,9 +11,16 @@ namespace cakf {
 // Points are stored pre-scaled as float4 by c = log2(e) sqrt(2 nu) / ell, so that the
 // scaled distance u' = log2(e) u (u = sqrt(2 nu) d / ell) feeds exp2 directly.
 //  Euclidean:    (c x, c y, c z, c^2 |x|^2); a row point is prepared once as
-//                (-2 c x, -2 c y, -2 c z, c^2 |x|^2) so that
-//                u'^2 = w_a + w_b - 2 <a, b> costs one add and three FMAs; the sqrt takes
-//                |u'^2| (a free source modifier) against rounding below zero.
+//                (-2 c x, -2 c y, -2 c z, c^2 |x|^2).  Two forms of u'^2 use this layout:
+//                the dot-product form w_a + w_b - 2 <a, b> (one add and three FMAs, or one
+//                FP32 MFMA per tile) and the difference form |b - a|^2 (three roundings of
+//                the differences).  The dot-product form leaves an absolute error of order
+//                eps (w_a + w_b) in u'^2, i.e. relative errors up to ~1e-5 in single kernel
+//                entries at the lengthscales used here, which ill-conditioned projected Gram
+//                matrices amplify to ~2e-5 in the posterior; the difference form keeps every
+//                entry within a few ulp.  kval (every FP32 product) takes the difference
+//                form; the dot-product form is kept for the BF16 block product and the
+//                BF16-mode action loop, whose MFMA distance it allows.
 //  Great-circle: (x, y, z, c) with unit (x, y, z) and u' = c theta,
 //                theta = 2 arcsin(|x - x'| / 2), the chord form of arccos(<x, x'>) that
 //                stays well conditioned for nearby points in FP32.
@@ -57,10 +64,9 @@ __device__ __forceinline__ float scaled_dist(const float4 ap, const float4 b) {
     }
 }
 
-// u' from coordinate differences (Euclidean).  The dot-product form above leaves an
-// absolute error of order eps |x|^2 in u'^2, i.e. order sqrt(eps) |x| in u' near u' = 0;
-// the Matern-3/2 and -5/2 correlations are flat to first order there, Matern-1/2 is not,
-// so it takes the differences: b - a = b + ap / 2 with one rounding per coordinate.
+// u' from coordinate differences (Euclidean): b - a = b + ap / 2 with one rounding per
+// coordinate (ap / 2 = -c a exactly).  Unlike the dot-product form it has no error of order
+// sqrt(eps) |x| in u' near u' = 0 and no cancellation against the norms.
 __device__ __forceinline__ float scaled_dist_diff(const float4 ap, const float4 b) {
     const float dx = __builtin_fmaf(0.5f, ap.x, b.x);
     const float dy = __builtin_fmaf(0.5f, ap.y, b.y);
@@ -68,10 +74,11 @@ __device__ __forceinline__ float scaled_dist_diff(const float4 ap, const float4 
     return __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
 }
 
-// Kernel entry k(a, b) for a prepared row point ap = prep_row(a) and a stored point b.
+// Kernel entry k(a, b) for a prepared row point ap = prep_row(a) and a stored point b
+// (Euclidean distances in the difference form).
 template <int NU2, int DIST>
 __device__ __forceinline__ float kval(const float4 ap, const float4 b) {
-    if constexpr (NU2 == 1 && DIST == DIST_EUCLID) return matern_u<NU2>(scaled_dist_diff(ap, b));
+    if constexpr (DIST == DIST_EUCLID) return matern_u<NU2>(scaled_dist_diff(ap, b));
     else return matern_u<NU2>(scaled_dist<DIST>(ap, b));
 }
 

@@ -49,9 +49,11 @@ void launch_colsum_partial(const float* A, int lda, int rows, int cols, const fl
                            int ldx, float* partial, int ldp, hipStream_t st, int* nblk_out);
 void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, float* out,
                          int ldo, hipStream_t st);
-void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
-                      int j, float* part, const float* mpart, int nmpart, float* T,
-                      const double* cpart, int ncpart, int gs, double* colvec,
+// mfma_dist: Euclidean Matern-3/2 and -5/2 take the squared distances from FP32 MFMA
+// (dot-product form); otherwise every entry uses the difference form on the VALU.
+void launch_sym_tiles(int nu2, int dist, bool mfma_dist, const float4* Xo, const float* S,
+                      const ObsDims& d, int j, float* part, const float* mpart, int nmpart,
+                      float* T, const double* cpart, int ncpart, int gs, double* colvec,
                       const LoopState* ls, hipStream_t st, hipEvent_t ev_start = nullptr,
                       hipEvent_t ev_stop = nullptr);
 void launch_form_u(const float* part, const float* S, float* U, const float* T,

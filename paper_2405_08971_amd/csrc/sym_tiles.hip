@@ -166,8 +166,9 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const float4* __restrict__ Xo
 // the tile's rows 32 w .. 32 w + 31 (two row sub-tiles) against all 128 columns (eight
 // column sub-tiles).  The 16 partial sums per row (one per lane column) and per column
 // (four lane rows times four waves) are combined in a fixed order as in k_sym_tiles.
-// The dot-product form of the distance is the one the VALU form uses for these kernels
-// (flat at u' = 0); Matern-1/2 and the great-circle distance keep k_sym_tiles.
+// The dot-product form of the distance (flat kernels at u' = 0 only) carries the larger
+// entry error described with the point layout: it serves the BF16 modes, while the FP32
+// mode, Matern-1/2 and the great-circle distance take k_sym_tiles (difference form).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int NU2>
@@ -265,9 +266,9 @@ __global__ __launch_bounds__(256) void k_sym_tiles_mfma(const float4* __restrict
     }
 }
 
-void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const ObsDims& d,
-                      int j, float* part, const float* mpart, int nmpart, float* T,
-                      const double* cpart, int ncpart, int gs, double* colvec,
+void launch_sym_tiles(int nu2, int dist, bool mfma_dist, const float4* Xo, const float* S,
+                      const ObsDims& d, int j, float* part, const float* mpart, int nmpart,
+                      float* T, const double* cpart, int ncpart, int gs, double* colvec,
                       const LoopState* ls, hipStream_t st, hipEvent_t ev_start,
                       hipEvent_t ev_stop) {
     const int nb = d.mp / SYM_TILE;
@@ -279,8 +280,8 @@ void launch_sym_tiles(int nu2, int dist, const float4* Xo, const float* S, const
     hipExtLaunchKernelGGL((k_sym_tiles_mfma<NUV>), dim3(tiles + n_t + n_c), dim3(256), 0, st, \
                           ev_start, ev_stop, 0, Xo, S, d, j, part, mpart, nmpart, n_t, T,     \
                           cpart, ncpart, gs, n_c, colvec, ls)
-    if (dist == DIST_EUCLID && nu2 == 5) { CAKF_SYM_MFMA(5); return; }
-    if (dist == DIST_EUCLID && nu2 == 3) { CAKF_SYM_MFMA(3); return; }
+    if (mfma_dist && dist == DIST_EUCLID && nu2 == 5) { CAKF_SYM_MFMA(5); return; }
+    if (mfma_dist && dist == DIST_EUCLID && nu2 == 3) { CAKF_SYM_MFMA(3); return; }
 #undef CAKF_SYM_MFMA
     CAKF_DISPATCH_KERNEL(nu2, dist,
         hipExtLaunchKernelGGL((k_sym_tiles<NU2, DIST>), dim3(tiles + n_t + n_c), dim3(256), 0,
