@@ -8,8 +8,11 @@ generated before the timed region and are resident in device memory.
 
 Prints one JSON line.  Besides the throughput it carries the roofline figures of the
 dominant kernel (the symmetric Matern tile matvec of the action loop, measured with HIP
-events on the library's stream over the timed region) and the FP64 oracle timed on a
-bounded sample of the same workload on the host cores.
+events on the library's stream over the timed region), the accuracy of both arithmetic
+modes against FP64 (the committed oracle reference of the first steps, and the oracle
+replaying the headline run's own actions), the headline mode against the FP32-plain one
+over the whole run, and the FP64 oracle timed on a bounded sample of the same workload on
+the host cores.
 """
 from __future__ import annotations
 
@@ -61,6 +64,10 @@ def parse():
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 256 MiB device copy (counter calibration)")
+    p.add_argument("--no-accuracy", action="store_true",
+                   help="skip the FP64-reference and precision-replay comparisons")
+    p.add_argument("--replay-steps", type=int, default=200,
+                   help="steps of the BF16X3-vs-FP32 replay with shared CG actions")
     return p.parse_args()
 
 
@@ -121,21 +128,6 @@ def run(cfg, X, inputs, warmup, steps, prec, breakdown=3, policy="cg", block_act
     return dict(elapsed=elapsed, prof=prof, phases=phases, mean=mean.cpu().numpy(),
                 var=var.cpu().numpy(), dropped=dropped, nonfinite=nonfinite,
                 recs=recs[:warmup + steps])
-
-
-def replay(cfg, X, inputs, recs, prec):
-    """The same steps with the actions of another run given as inputs (untimed): the
-    difference between two such runs is due to arithmetic precision alone, since the
-    CG actions of a run depend on every rounding before them."""
-    import torch
-    f = make_filter(cfg, X, prec, policy="given")
-    for (idx, y), rec in zip(inputs, recs):
-        f.step(idx, y, rec.S)
-    torch.cuda.synchronize()
-    mean, _ = f.state()
-    var = f.marginal_var()
-    f.close()
-    return mean.cpu().numpy(), var.cpu().numpy()
 
 
 def traffic_per_launch(kernel):
@@ -318,46 +310,143 @@ def next_rows(seed=0):
     return out
 
 
-def cpu_baseline(cfg, wl):
-    """The FP64 oracle on a bounded sample of one step of the same workload.
+def err_fields(x, ref):
+    """Relative mean error mean|x - ref| / mean|ref| and the worst single entry on the same
+    scale, max|x - ref| / mean|ref|."""
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = float(np.mean(np.abs(ref)))
+    return float(np.mean(np.abs(x - ref)) / den), float(np.max(np.abs(x - ref)) / den)
 
-    Sample: a quarter of the rows of one projected-Gram product Ghat v (the unit of the
-    action loop; the oracle's iterative update makes three per action plus one batch
-    product for the log-likelihood), the block product on 1/64 of the state rows, and
-    one truncation of an n x (r + i) factor.  Seconds per step are extrapolated as
-    (3 i + 1) * 4 t_Ghat_quarter + 64 t_block_slice + t_truncate."""
-    from oracle.cakf import Model, truncate
+
+def vs_fp64_reference(cfg, X, wl, prec):
+    """The first steps of the workload with the input generator's Gaussian actions against
+    the committed FP64 reference (tests/golden/sphere_n65536_fp64.npz, written by the
+    oracle), per result: the mean, the marginal variance before and after the truncation
+    (steps 5 and 6 truncate 640 -> 512 columns) and the log-likelihood term.  Worst step."""
+    import torch
+    from paper_2405_08971_amd.filter import Record
+    path = os.path.join(ROOT, "tests", "golden", "sphere_n65536_fp64.npz")
+    if cfg.name != "sphere_n65536" or not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    sub = ref["subset"]
+    rows = torch.from_numpy(sub.astype(np.int32)).cuda()
+    f = make_filter(cfg, X, prec, policy="given")
+    worst = {}
+    for k in range(1, ref["mean"].shape[0] + 1):
+        idx, y = wl.step(k)
+        rec = Record(cfg.m, cfg.i)
+        f.predict()
+        f.update(torch.from_numpy(idx.astype(np.int32)).cuda(),
+                 torch.from_numpy(y.astype(np.float32)).cuda(),
+                 torch.from_numpy(wl.actions(k).astype(np.float32)).cuda(), rec)
+        mean, _ = f.state()
+        got = {"mean": mean[rows.long()].cpu().numpy(),
+               "var": f.marginal_var(rows).cpu().numpy()}
+        f.truncate()
+        got["var_trunc"] = f.marginal_var(rows).cpu().numpy()
+        for key, v in got.items():
+            e_mean, e_max = err_fields(v, ref[key][k - 1])
+            worst[key] = max(worst.get(key, 0.0), e_mean)
+            worst[key + "_max"] = max(worst.get(key + "_max", 0.0), e_max)
+        ll = float(rec.loglik.item())
+        worst["loglik"] = max(worst.get("loglik", 0.0),
+                              abs(ll - ref["loglik"][k - 1]) / abs(ref["loglik"][k - 1]))
+    f.close()
+    worst["steps"] = int(ref["mean"].shape[0])
+    return worst
+
+
+def precision_replay(cfg, X, wl, T, keep=2):
+    """The headline mode with CG actions and, in lockstep, the FP32-plain path replaying
+    those actions, over T steps (untimed).  CG actions depend on every rounding before
+    them, so two free runs are not comparable; with the actions shared the difference is
+    due to arithmetic precision alone.  Per step: relative mean difference of the mean and
+    of the marginal variance on the 2048-point subset; the maximum over steps is reported.
+    The first `keep` steps' actions and subset results of both runs are returned for the
+    FP64 replay of the CPU-baseline leg."""
+    import torch
+    from paper_2405_08971_amd.filter import Record
+    sub = wl.subset(2048)
+    rows = torch.from_numpy(sub.astype(np.int32)).cuda()
+    fa = make_filter(cfg, X, "bf16x3", policy="cg")
+    fb = make_filter(cfg, X, "fp32", policy="given")
+    worst = {"mean": 0.0, "var": 0.0, "mean_step": 0, "var_step": 0}
+    kept = []
+    for k in range(1, T + 1):
+        idx, y = wl.step(k)
+        idx_d = torch.from_numpy(idx.astype(np.int32)).cuda()
+        y_d = torch.from_numpy(y.astype(np.float32)).cuda()
+        rec = Record(cfg.m, cfg.i)
+        fa.step(idx_d, y_d, record=rec)
+        fb.step(idx_d, y_d, rec.S)
+        ma, va = fa.state()[0][rows.long()].cpu().numpy(), fa.marginal_var(rows).cpu().numpy()
+        mb, vb = fb.state()[0][rows.long()].cpu().numpy(), fb.marginal_var(rows).cpu().numpy()
+        for key, x, r in (("mean", ma, mb), ("var", va, vb)):
+            e = err_fields(x, r)[0]
+            if e > worst[key]:
+                worst[key], worst[key + "_step"] = e, k
+        if k <= keep:
+            na = int(rec.n_actions.item())
+            kept.append(dict(idx=idx, y=y, S=rec.S.cpu().numpy()[:, :na],
+                             bf16x3=(ma, va), fp32=(mb, vb)))
+    worst["final"] = {"mean": err_fields(ma, mb)[0], "var": err_fields(va, vb)[0]}
+    worst["steps"] = T
+    fa.close()
+    fb.close()
+    return worst, kept
+
+
+def cpu_baseline(cfg, wl, kept):
+    """The FP64 oracle timed on the host cores on a bounded sample of the same workload:
+    the first len(kept) steps, with the batch update of Alg. 2 conditioning on the actions
+    the GPU's CG run took (the oracle's form for given actions) and the truncation of
+    Sec. 3.2.  Seconds per step are measured, not extrapolated.  The same run gives the
+    FP64 error of the GPU's CG steps (both modes) on the 2048-point subset."""
+    from oracle.cakf import Model, run_filter
+    threads = max(1, min(16, os.cpu_count() or 1))
+    os.environ["ORACLE_THREADS"] = str(threads)
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(threads)
     except Exception:
-        threads = 1
-    model = Model(wl.X, cfg.nu2, cfg.ell, cfg.sigma_f2, cfg.a, cfg.noise_var, cfg.dist)
-    idx, y = wl.step(1)
-    rng = np.random.default_rng(0)
-    r0 = np.asarray(y, np.float64)
-    Mo = 0.01 * rng.standard_normal((cfg.m, cfg.r))
-    q = cfg.m // 4
-    t = time.perf_counter()
-    _ = (model.cov_matmul(idx[:q], idx, r0) - Mo[:q] @ (Mo.T @ r0)
-         + cfg.noise_var * r0[:q])
-    t_ghat = (time.perf_counter() - t) * 4
-    rows = np.arange(0, cfg.n, 64)
-    B = rng.standard_normal((cfg.m, cfg.i + 1))
-    t = time.perf_counter()
-    _ = model.cov_matmul(rows, idx, B)
-    t_block = (time.perf_counter() - t) * 64
-    M = rng.standard_normal((cfg.n, cfg.r + cfg.i)).astype(np.float64)
-    t = time.perf_counter()
-    _ = truncate(M, cfg.r)
-    t_trunc = time.perf_counter() - t
-    s_per_step = (3 * cfg.i + 1) * t_ghat + t_block + t_trunc
-    return dict(value=1.0 / s_per_step, unit="steps/s", cores=threads, kind="oracle",
-                sample=(f"one step of {cfg.name}: 1/4 of a Ghat product (x4: {t_ghat:.1f} s), block "
-                        f"product on 1/64 of the rows (x64: {t_block:.1f} s), one "
-                        f"truncation ({t_trunc:.2f} s); s/step = (3i+1) t_Ghat + block + "
-                        f"truncation = {s_per_step:.0f} s; elementwise kernel evaluation "
-                        f"is single-threaded NumPy, BLAS uses {threads} threads"))
+        limit = None
+    X = wl.X.astype(np.float32).astype(np.float64)
+    model = Model(X, cfg.nu2, cfg.ell, cfg.sigma_f2, cfg.a, cfg.noise_var, cfg.dist)
+    steps = [(s["idx"].astype(np.int64), s["y"].astype(np.float32).astype(np.float64))
+             for s in kept]
+    acts = [s["S"].astype(np.float64) for s in kept]
+    t0 = time.perf_counter()
+    recs = run_filter(model, steps, cfg.i, cfg.r, policy="given", actions=acts, form="batch")
+    elapsed = time.perf_counter() - t0
+    if limit is not None:
+        limit.restore_original_limits()
+    sub = wl.subset(2048)
+    err = {}
+    for prec in ("bf16x3", "fp32"):
+        e = {}
+        for k, (s, rec) in enumerate(zip(kept, recs)):
+            for key, x, r in (("mean", s[prec][0], rec.m[sub]),
+                              ("var", s[prec][1],
+                               cfg.sigma_f2 - np.sum(rec.M_plus[sub] ** 2, axis=1))):
+                em, ex = err_fields(x, r)
+                e[key] = max(e.get(key, 0.0), em)
+                e[key + "_max"] = max(e.get(key + "_max", 0.0), ex)
+        err[prec] = e
+    try:
+        import platform
+        model_name = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                           if ln.startswith("model name")), platform.processor())
+    except Exception:
+        model_name = "unknown"
+    base = dict(value=len(kept) / elapsed, unit="steps/s", cores=threads, kind="oracle",
+                sample=(f"first {len(kept)} steps of {cfg.name} ({elapsed:.1f} s, "
+                        f"{elapsed / len(kept):.1f} s/step measured): the FP64 oracle's batch "
+                        f"update (Alg. 2) on the GPU run's CG actions, then its truncation; "
+                        f"kernel products over {threads} threads, BLAS {threads} threads; "
+                        f"host: {model_name}"))
+    return base, err
 
 
 def main():
@@ -432,14 +521,20 @@ def main():
             "ms_per_step": fp32["elapsed"] / args.steps * 1e3,
             "phases_ms_per_step": fp32["phases"],
         }
-        # precision alone: the FP32-plain path replaying the headline run's actions
-        mref, vref = replay(cfg, X, inputs, res["recs"], "fp32")
-        sub = wl.subset(2048)
-        line["fp32_plain"]["replay_rel_diff"] = {
-            "mean": float(np.mean(np.abs(res["mean"][sub] - mref[sub]))
-                          / np.mean(np.abs(mref[sub]))),
-            "var": float(np.mean(np.abs(res["var"][sub] - vref[sub]))
-                         / np.mean(np.abs(vref[sub])))}
+    cg_loglik = float(np.mean([rec.loglik.item() for rec in res["recs"][args.warmup:]]))
+    del res, fp32
+    torch.cuda.empty_cache()
+    # accuracy: both modes against the FP64 reference (given actions), and the headline
+    # mode against the FP32-plain path over the whole run with shared CG actions
+    kept = []
+    if not args.no_accuracy:
+        acc = {"note": "relative mean error mean|x - x64| / mean|x64| and worst entry "
+                       "max|x - x64| / mean|x64| on the seeded 2048-point subset"}
+        for prec in ("bf16x3", "fp32"):
+            acc[f"vs_fp64_given_actions_{prec}"] = vs_fp64_reference(cfg, X, wl, prec)
+        T = min(args.replay_steps, cfg.T)
+        acc["bf16x3_vs_fp32_replay"], kept = precision_replay(cfg, X, wl, T)
+        line["accuracy"] = acc
     if not args.no_next_rows:
         line["next_rows"] = next_rows(args.seed)
         # the block-residual policy on the same workload and inputs (same action budget)
@@ -452,8 +547,7 @@ def main():
                              "loglik_per_step": float(np.mean(
                                  [rec.loglik.item() for rec in r["recs"][args.warmup:]])),
                              "dropped_actions": r["dropped"]}
-        blk["cg_loglik_per_step"] = float(np.mean(
-            [rec.loglik.item() for rec in res["recs"][args.warmup:]]))
+        blk["cg_loglik_per_step"] = cg_loglik
         blk["workload"] = line["config"]["workload"].replace("CG actions",
                                                              "block-residual actions")
         blk["note"] = "the same inputs as the headline run, timed the same way"
@@ -469,8 +563,11 @@ def main():
             "value": args.steps / r32["elapsed"],
             "ms_per_step": r32["elapsed"] / args.steps * 1e3,
             "dropped_actions": r32["dropped"]}
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, wl)
+    if not args.no_cpu_baseline and kept:
+        line["cpu_baseline"], err = cpu_baseline(cfg, wl, kept)
+        line["accuracy"]["vs_fp64_cg_actions"] = dict(
+            err, steps=len(kept), note="the FP64 oracle replaying the headline run's CG "
+                                       "actions (the FP32 path replays the same actions)")
     print(json.dumps(line), flush=True)
 
 

@@ -57,12 +57,16 @@ typedef struct cakf_ctx cakf_ctx;
 #define CAKF_DIST_GEODESIC 1
 
 /* Arithmetic of the kernel-matrix x block product P^- H^T [W w] (Alg. 2):
- *  FP32   - FP32 kernel tiles, FP32 contraction;
+ *  FP32   - FP32 kernel tiles, FP32 MFMA contraction of 64 observations at a time, the
+ *           chunk sums added in FP64;
  *  BF16   - FP32 kernel tiles rounded to BF16, BF16 MFMA with FP32 accumulation;
  *  BF16X3 - BF16 MFMA on split operands: K = Kh + Kl, B = Bh + Bl (each part BF16),
  *           Y = Kh Bh + Kl Bh + Kh Bl, which restores close to FP32 accuracy.
  * The observation-space loop (actions, Gram matrix) always runs in FP32 with FP64
- * small matrices. */
+ * small matrices.  In FP32 mode every kernel entry takes its Euclidean distance from
+ * coordinate differences; the BF16 modes form the squared distances of the Euclidean
+ * Matern-3/2 and -5/2 kernels on FP32 MFMA from norms and dot products, which is faster
+ * but leaves relative errors up to ~1e-5 in single entries. */
 #define CAKF_PREC_FP32   0
 #define CAKF_PREC_BF16   1
 #define CAKF_PREC_BF16X3 2
@@ -75,7 +79,7 @@ typedef struct cakf_ctx cakf_ctx;
  * groups of the observations (group g of b = [floor(g m / b), floor((g + 1) m / b))),
  * so that one kernel-matrix product with b vectors serves the whole round.  The last
  * round takes the actions left (b_t = min(b, actions left)); resid_tol must be 0 with
- * BLOCK (cakf_create returns CAKF_E_ARG otherwise). */
+ * BLOCK and GIVEN (cakf_create returns CAKF_E_ARG otherwise). */
 #define CAKF_POLICY_CG    0
 #define CAKF_POLICY_GIVEN 1
 #define CAKF_POLICY_BLOCK 2
@@ -113,7 +117,10 @@ typedef struct {
     int policy;             /* CAKF_POLICY_*                                         */
     int block_actions;      /* actions per round of POLICY_BLOCK, 1..max_actions
                                (ignored by the other policies)                       */
-    double resid_tol;       /* stop when ||r|| <= resid_tol * ||r0||; 0 = never     */
+    double resid_tol;       /* stop when ||r|| <= resid_tol * ||r0||; 0 = never;
+                               POLICY_CG only (the stop compares the norms of the
+                               residual actions; cakf_create returns CAKF_E_ARG for
+                               resid_tol != 0 with another policy)                  */
     double pivot_tol;       /* drop action j when its Ghat-orthogonal part keeps no
                                more than pivot_tol of s_j^T Ghat s_j (breakdown);
                                typical 1e-10                                         */
@@ -356,14 +363,19 @@ typedef struct {
 
 /* Derivative of the log-likelihood of cakf_loglik over the T steps of tape (a run from
  * the prior with this context's parameters) with respect to
- *   grad[0] the spatial lengthscale, grad[1] the OU coefficient a,
+ *   grad[0] the spatial lengthscale,
+ *   grad[1] the temporal lengthscale ell_t = -dt / log(a) when dt > 0 (the time step the
+ *           OU coefficient a = exp(-dt / ell_t) was formed with), or the OU coefficient a
+ *           itself when dt == 0,
  *   grad[2] the signal variance,      grad[3] the noise variance,
  * holding the actions and the truncation rotations fixed at their recorded values (the
- * derivative of the filter as it was run).  Reverse sweep over the steps: kernel tiles
- * are recomputed, nothing of size n x m is stored.  Needs cfg.gradient != 0, the
- * context's max_actions <= 159 and distinct indices within each step.  grad: host,
- * 4 doubles.  Synchronises the stream. */
-int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double* grad);
+ * derivative of the filter as it was run; the paper leaves evidence maximisation to future
+ * work, Sec. 8).  Reverse sweep over the steps of Alg. 1 and Alg. 2: kernel tiles are
+ * recomputed, nothing of size n x m is stored.  Needs cfg.gradient != 0, the context's
+ * max_actions <= 159 and distinct indices within each step; dt < 0 is CAKF_E_ARG.
+ * grad: host, 4 doubles.  Synchronises the stream. */
+int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double dt,
+                     double* grad);
 
 /* Phases timed by the profiling hooks (HIP events on the context stream around each
  * launch of the phase). */

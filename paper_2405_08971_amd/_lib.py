@@ -119,7 +119,7 @@ def lib() -> ctypes.CDLL:
             "cakf_sample_lift": (i, [vp, i, vp, vp, i, vp]),
             "cakf_sample_backward": (i, [vp, i, vp, vp, i, i,
                                          ctypes.POINTER(cakf_sample_input), vp, vp, vp, vp]),
-            "cakf_loglik_grad": (i, [vp, i, ctypes.POINTER(cakf_tape_step),
+            "cakf_loglik_grad": (i, [vp, i, ctypes.POINTER(cakf_tape_step), d,
                                      ctypes.POINTER(d)]),
             "cakf_profile_enable": (i, [vp, i]),
             "cakf_profile_stride": (i, [vp, i]),
@@ -249,11 +249,12 @@ def cakf_loglik(ctx: int):
     return v.value, n.value
 
 
-def cakf_loglik_grad(ctx: int, tape) -> list:
-    """tape: a sequence of cakf_tape_step; returns the 4 derivatives (host doubles)."""
+def cakf_loglik_grad(ctx: int, tape, dt: float = 0.0) -> list:
+    """tape: a sequence of cakf_tape_step; returns the 4 derivatives (host doubles), the
+    second with respect to ell_t when dt > 0, else with respect to the OU coefficient."""
     arr = (cakf_tape_step * len(tape))(*tape)
     g = (ctypes.c_double * 4)()
-    check(lib().cakf_loglik_grad(ctx, len(tape), arr, g), "cakf_loglik_grad")
+    check(lib().cakf_loglik_grad(ctx, len(tape), arr, dt, g), "cakf_loglik_grad")
     return list(g)
 
 

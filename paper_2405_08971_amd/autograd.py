@@ -5,8 +5,8 @@ theta = (lengthscale, ell_t, signal_var, noise_var) (a float64 tensor of 4) and 
 the sum of the projected log-likelihood terms (cakf_loglik).  Its backward calls the
 library's reverse sweep (cakf_loglik_grad), which differentiates the filter as it was run:
 the actions and the truncation rotations of the forward pass are held fixed.  The OU
-coefficient a = exp(-dt / ell_t) is the library's parameter; its derivative is mapped to
-ell_t here (da / dell_t = a dt / ell_t^2), which is the only arithmetic in this module.
+coefficient a = exp(-dt / ell_t) is the library's parameter; given dt, the library returns
+the derivative with respect to ell_t itself, so this module only marshals arguments.
 
 The forward pass keeps, per step, the record, the filtered mean, the truncated factor and
 the truncation rotation (the tape of the reverse sweep) in device tensors until backward.
@@ -74,20 +74,16 @@ class FilterLogLik(torch.autograd.Function):
         value, _ = f.loglik()
         ctx.filter = f
         ctx.tape = tape
-        ctx.a = a
         ctx.dt = opts["dt"]
-        ctx.ell_t = ell_t
         return torch.tensor(value, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, g):
         f = ctx.filter
-        d = f.loglik_grad(ctx.tape.steps)
+        d = f.loglik_grad(ctx.tape.steps, ctx.dt)
         f.close()
         ctx.tape = None
-        d_ell_t = d[1] * ctx.a * ctx.dt / ctx.ell_t ** 2
-        grad = torch.tensor([d[0], d_ell_t, d[2], d[3]], dtype=torch.float64) * g.cpu()
-        return grad, None, None, None, None
+        return torch.tensor(d, dtype=torch.float64) * g.cpu(), None, None, None, None
 
 
 def loglik(theta: torch.Tensor, X: torch.Tensor, steps: Sequence, *, nu2: int = 3,

@@ -236,8 +236,11 @@ static int validate(const cakf_config* c) {
         c->policy != CAKF_POLICY_BLOCK)
         return CAKF_E_ARG;
     if (c->policy == CAKF_POLICY_BLOCK &&
-        (c->block_actions < 1 || c->block_actions > c->max_actions || c->resid_tol != 0))
+        (c->block_actions < 1 || c->block_actions > c->max_actions))
         return CAKF_E_ARG;
+    // the residual-tolerance stop reads ||r_j||^2 = s_j^T s_j, which holds only when the
+    // actions are the residuals (CG)
+    if (c->resid_tol != 0 && c->policy != CAKF_POLICY_CG) return CAKF_E_ARG;
     if (c->prec != CAKF_PREC_FP32 && c->prec != CAKF_PREC_BF16 && c->prec != CAKF_PREC_BF16X3)
         return CAKF_E_ARG;
     if (c->resid_tol < 0 || c->pivot_tol < 0) return CAKF_E_ARG;
@@ -667,9 +670,9 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     for (int j = 0; j < (block ? 0 : imax); ++j) {
         {
             KernelTimer t(c, CAKF_PHASE_SYM_TILES);
-            launch_sym_tiles(nu2, dist, c->Xo, c->S, d, j, c->part,
-                             (cg && j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart, c->T,
-                             c->cpart, ncp, c->gs, c->colvec, c->ls, st, t.start, t.stop);
+            launch_sym_tiles(nu2, dist, c->cfg.prec != CAKF_PREC_FP32, c->Xo, c->S, d, j,
+                             c->part, (cg && j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart,
+                             c->T, c->cpart, ncp, c->gs, c->colvec, c->ls, st, t.start, t.stop);
         }
         int nfu = 0;
         {
@@ -781,8 +784,9 @@ extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
 
 
 // ------------------------------------------------------- log-likelihood derivative
-extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, double* grad) {
-    if (!c || !grad || T < 1 || !tape || !c->gMb[0]) return CAKF_E_ARG;
+extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, double dt,
+                                double* grad) {
+    if (!c || !grad || T < 1 || !tape || !c->gMb[0] || !(dt >= 0)) return CAKF_E_ARG;
     hipStream_t st = c->stream;
     const int n = c->n, imax = c->imax, bp = c->bp, ldM = c->ldM, ldmo = c->ldmo;
     const int I1 = imax + 1;
@@ -903,6 +907,11 @@ extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, 
     }
     HIP_TRY(hipMemcpyAsync(grad, c->gacc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (dt > 0) {
+        // a = exp(-dt / ell_t):  da / dell_t = a dt / ell_t^2 = a (log a)^2 / dt
+        const double la = std::log(c->cfg.ou_coeff);
+        grad[1] *= c->cfg.ou_coeff * la * la / dt;
+    }
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 

@@ -253,10 +253,12 @@ class CAKF:
                                out_var)
         return out_mean, out_var, (out_fac[:, :r] if want_factor else None)
 
-    def loglik_grad(self, tape) -> list:
-        """d loglik / d(lengthscale, ou_coeff, signal_var, noise_var) over a recorded run
-        (a sequence of cakf_tape_step; see paper_2405_08971_amd.autograd)."""
-        return L.cakf_loglik_grad(self.ctx, tape)
+    def loglik_grad(self, tape, dt: float = 0.0) -> list:
+        """d loglik / d(lengthscale, ell_t, signal_var, noise_var) over a recorded run (a
+        sequence of cakf_tape_step; see paper_2405_08971_amd.autograd), with ell_t the
+        temporal lengthscale at time step dt > 0; dt = 0 gives d / d ou_coeff in place of
+        d / d ell_t."""
+        return L.cakf_loglik_grad(self.ctx, tape, dt)
 
     def profile(self, on=True, every=1):
         """on: True (all phases), False (off), or an iterable of phase names; every: time

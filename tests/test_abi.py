@@ -53,3 +53,23 @@ def test_binding_wraps_every_declared_function():
     from paper_2405_08971_amd import _lib
     for n in declared_functions():
         assert hasattr(_lib, n), n
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcakf.so not built")
+def test_residual_tolerance_is_rejected_without_cg_actions():
+    """cakf_create validates its arguments before any device call: the residual-tolerance
+    stop is defined for residual (CG) actions only, so GIVEN and BLOCK with resid_tol != 0
+    are argument errors (for CG the value passes validation)."""
+    from paper_2405_08971_amd import _lib
+    lib = ctypes.CDLL(LIB)
+    dummy = ctypes.c_float(0.0)
+    for policy, expect_arg_error in (("given", True), ("block", True)):
+        cfg = _lib.cakf_config(n=16, dim=3, X=ctypes.cast(ctypes.pointer(dummy), ctypes.c_void_p),
+                               kernel=3, dist=0, lengthscale=0.3, signal_var=1.0,
+                               noise_var=0.05, ou_coeff=0.8, temporal=0, max_obs=8,
+                               max_actions=4, max_rank=4, policy=_lib.POLICY[policy],
+                               block_actions=2, resid_tol=1e-3, pivot_tol=1e-10, prec=0)
+        ctx = ctypes.c_void_p()
+        rc = lib.cakf_create(ctypes.byref(cfg), ctypes.byref(ctx))
+        assert rc == _lib.CAKF_E_ARG, (policy, rc)
+        assert not ctx.value

@@ -90,3 +90,37 @@ def test_gradient_on_the_sphere_geodesic():
     cfg = small_config("ggeo", dist=1, n=600, m=200, i=8, r=12, T=4)
     _, g, _, g_tan, _ = _run(cfg, seed=31)
     _check(g, g_tan, GRAD_TOL)
+
+
+def test_given_action_gradient_with_the_oracles_own_rotations():
+    """Given actions, and the oracle computes its own truncation rotations (FP64 eigh of its
+    own M^T M at the base parameters) instead of replaying the GPU's: the frozen-rotation
+    likelihood depends on the rotation only through the projector V_r V_r^T, which both
+    sides agree on, so the derivatives must agree without any GPU-produced input."""
+    import torch
+    from paper_2405_08971_amd.autograd import FilterLogLik
+    from oracle.cakf import run_filter
+
+    cfg = small_config("ggiv", n=500, m=160, i=6, r=10, T=5)
+    X, steps, actions = inputs(cfg, seed=32, missing_steps=(3,), policy="given")
+    dt = 1.0
+    theta0 = (cfg.ell, cfg.ell_t, cfg.sigma_f2, cfg.noise_var)
+    dev_steps = [None if s is None else (torch.from_numpy(s[0]).cuda(),
+                                         torch.from_numpy(s[1]).cuda()) for s in steps]
+    dev_acts = [None if a is None else torch.from_numpy(a).cuda() for a in actions]
+    theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    opts = dict(nu2=cfg.nu2, dist="euclid", dt=dt, max_obs=cfg.m, max_actions=cfg.i,
+                max_rank=cfg.r, policy="given", pivot_tol=1e-10, prec="fp32")
+    ll = FilterLogLik.apply(theta, torch.from_numpy(X).cuda(), dev_steps, dev_acts, opts)
+    ll.backward()
+    g = theta.grad.numpy().copy()
+    base = model_at(Model(X.astype(np.float64), cfg.nu2, cfg.ell, cfg.sigma_f2, cfg.a,
+                          cfg.noise_var, cfg.dist), dt, theta0)
+    ost = [None if s is None else (s[0].astype(np.int64), s[1].astype(np.float64))
+           for s in steps]
+    acts = [None if a is None else a.astype(np.float64) for a in actions]
+    recs = run_filter(base, ost, cfg.i, cfg.r, policy="given", actions=acts)
+    assert sum(r.V_r is not None for r in recs) >= 2     # the rotations are the oracle's
+    value, g_tan = tangent.replay_tangent(base, dt, theta0, ost, recs)
+    assert abs(float(ll.item()) - value) <= 1e-5 * abs(value), (float(ll.item()), value)
+    _check(g, g_tan, GRAD_TOL)
