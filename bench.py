@@ -64,6 +64,9 @@ def parse():
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 256 MiB device copy (counter calibration)")
+    p.add_argument("--rate-probe", action="store_true",
+                   help="only measure the VALU issue rates of exp2, sqrt and fma (the "
+                        "transcendental peak of the roofline)")
     p.add_argument("--no-accuracy", action="store_true",
                    help="skip the FP64-reference and precision-replay comparisons")
     p.add_argument("--replay-steps", type=int, default=200,
@@ -164,6 +167,21 @@ def copy_probe():
         torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": a.numel() * 4, "launches": 3}), flush=True)
+
+
+def rate_probe():
+    """Issue rates of v_exp_f32, v_sqrt_f32 and v_fma_f32 measured by the library's probe
+    kernels (cakf_profile_rates), also as lanes per clock per CU at the 2.4 GHz peak clock
+    of the 256 CUs: the transcendental peak PEAK_TRANS assumes 32 (half the FP32 rate)."""
+    import torch
+    from paper_2405_08971_amd import _lib as L
+    torch.cuda.init()
+    rates = L.cakf_profile_rates()
+    out = {}
+    for name, v in zip(("exp2", "sqrt", "fma"), rates):
+        out[name] = {"lanes_per_s": v, "lanes_per_clk_per_cu": v / (256 * 2.4e9)}
+    out["peak_trans_assumed"] = PEAK_TRANS
+    print(json.dumps(out), flush=True)
 
 
 def next_rows(seed=0):
@@ -458,6 +476,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.rate_probe:
+        rate_probe()
         return
     import torch
     from paper_2405_08971_amd.workload import CONFIGS, Workload

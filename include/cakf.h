@@ -412,6 +412,15 @@ int cakf_profile_stride(cakf_ctx* ctx, int every);
  * stream. */
 int cakf_profile_read(cakf_ctx* ctx, double* total_ms, int* launches);
 
+/* Issue rates of the current device for the VALU instructions the kernel-matrix products
+ * are built from, the peaks their roofline figures are quoted against: lanes_per_s[0..2]
+ * = lane operations per second of v_exp_f32, v_sqrt_f32 and v_fma_f32, each measured by
+ * a kernel of dependent chains (eight independent chains per lane, every SIMD full; best
+ * of three timed launches on the null stream).  A measurement utility, not part of the
+ * filter: it allocates and frees a small buffer and synchronises the device.  No context
+ * is needed. */
+int cakf_profile_rates(double* lanes_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -124,6 +124,7 @@ def lib() -> ctypes.CDLL:
             "cakf_profile_enable": (i, [vp, i]),
             "cakf_profile_stride": (i, [vp, i]),
             "cakf_profile_read": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(i)]),
+            "cakf_profile_rates": (i, [ctypes.POINTER(d)]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -290,3 +291,11 @@ def cakf_smooth(ctx: int, steps, mean_out=None, var_out=None) -> None:
     """steps: a sequence of cakf_smooth_input, k = 1..T."""
     arr = (cakf_smooth_input * len(steps))(*steps)
     check(lib().cakf_smooth(ctx, len(steps), arr, ptr(mean_out), ptr(var_out)), "cakf_smooth")
+
+
+def cakf_profile_rates() -> list:
+    """Lane operations per second of v_exp_f32, v_sqrt_f32 and v_fma_f32 on the current
+    device (measured by the library's probe kernels)."""
+    out = (ctypes.c_double * 3)()
+    check(lib().cakf_profile_rates(out), "cakf_profile_rates")
+    return list(out)

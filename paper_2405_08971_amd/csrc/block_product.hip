@@ -164,7 +164,9 @@ static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const 
 // with the kernel matrix cancel by two to three orders of magnitude, and a plain FP32
 // sum over m = 600 observations already left ~1e-5 in the posterior variance.
 constexpr int F32_KC = 64;
-constexpr int F32_MAXNT = 5;     // column tiles per launch (FP64 accumulators: 32 VGPRs each)
+constexpr int F32_MAXNT = 3;     // column tiles per launch (FP64 accumulators: 32 VGPRs each;
+                                 // 5 tiles need 256 VGPRs, one wave per SIMD: 9.0 ms
+                                 // against 5.0 ms at n = 65536)
 template <int NU2, int DIST, int NT>
 __global__ __launch_bounds__(256) void k_block_mfma32(const float4* __restrict__ Xs, int n,
                                                       const float4* __restrict__ Xo, int m,

@@ -727,14 +727,35 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 
+// Device memory the truncation works in: the FP64 Gram (its buffer then holds the
+// tridiagonal's eigenvectors), the Gram's slab partials, the tridiagonalisation's
+// reflectors, tau, exchange vectors and barrier words, the tridiagonal (d, e), the
+// solver's info word and V_r.
+struct TruncWork {
+    double* G;
+    double* gwork;
+    size_t gwork_elems;
+    double *tdV, *tdtau, *tdp, *tdrow;   // tdV == nullptr: no one-launch tridiagonalisation
+    unsigned* tdctr;
+    int* tdabort;
+    double *eigval, *offdiag;
+    int* info;
+    float* Vr;
+};
+
+static TruncWork context_work(cakf_ctx* c) {
+    return TruncWork{c->G, c->gwork, c->gram_work_elems, c->tdV, c->tdtau, c->tdp, c->tdrow,
+                     c->tdctr, c->tdabort, c->eigval, c->offdiag, c->info, c->Vr};
+}
+
 // Replace the rows x K factor M (row-major, ld) by M V_r in Mout (ld ldo), V_r the leading
 // r eigenvectors of M^T M (FP64 Gram, FP64 symmetric eigensolver, FP32 rotation).
-static int truncate_factor(cakf_ctx* c, const float* M, int rows, int ld, int K, int r,
-                           float* Mout, int ldo, double* rotation) {
+static int truncate_factor(cakf_ctx* c, const TruncWork& w, const float* M, int rows, int ld,
+                           int K, int r, float* Mout, int ldo, double* rotation) {
     hipStream_t st = c->stream;
     {
         PhaseTimer t(c, CAKF_PHASE_GRAM);
-        launch_gram64(M, rows, ld, K, c->G, c->gwork, c->gram_work_elems, st);
+        launch_gram64(M, rows, ld, K, w.G, w.gwork, w.gwork_elems, st);
     }
     bool picked = false;
     {
@@ -742,13 +763,13 @@ static int truncate_factor(cakf_ctx* c, const float* M, int rows, int ld, int K,
         // G = Q T Q^T in one cooperative launch, T's eigenvectors by divide and conquer,
         // then only the r leading ones back-transformed (into V_r directly).  Larger K, or
         // a device that cannot co-schedule the launch, takes the library's dense solver.
-        if (c->tdV && K >= 3 && K <= TD_MAXK) {
-            if (launch_tridiag(c->G, K, c->tdV, c->tdtau, c->eigval, c->offdiag, c->tdp,
-                               c->tdrow, c->tdctr, c->tdabort, st) == hipSuccess) {
-                hipLaunchKernelGGL(k_note_abort, dim3(1), dim3(1), 0, st, c->tdabort, c->diag);
-                BLAS_TRY(rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, K, c->eigval,
-                                          c->offdiag, c->G, K, c->info));
-                launch_backtransform(c->G, c->tdV, c->tdtau, K, r, c->Vr, rotation, st);
+        if (w.tdV && K >= 3 && K <= TD_MAXK) {
+            if (launch_tridiag(w.G, K, w.tdV, w.tdtau, w.eigval, w.offdiag, w.tdp, w.tdrow,
+                               w.tdctr, w.tdabort, st) == hipSuccess) {
+                hipLaunchKernelGGL(k_note_abort, dim3(1), dim3(1), 0, st, w.tdabort, c->diag);
+                BLAS_TRY(rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, K, w.eigval,
+                                          w.offdiag, w.G, K, w.info));
+                launch_backtransform(w.G, w.tdV, w.tdtau, K, r, w.Vr, rotation, st);
                 picked = true;
             } else {
                 (void)hipGetLastError();
@@ -756,16 +777,16 @@ static int truncate_factor(cakf_ctx* c, const float* M, int rows, int ld, int K,
         }
         if (!picked)
             BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K,
-                                      c->G, K, c->eigval, c->offdiag, c->info));
+                                      w.G, K, w.eigval, w.offdiag, w.info));
     }
     {
         PhaseTimer t(c, CAKF_PHASE_ROTATE);
-        if (!picked) launch_pick_rotation(c->G, K, r, c->Vr, rotation, st);
+        if (!picked) launch_pick_rotation(w.G, K, r, w.Vr, rotation, st);
         const float one = 1.0f, zero = 0.0f;
         // Mout (row-major n x r) = M V_r: column-major (r x n) = V_r^T (r x K) M^T (K x n),
         // V_r row-major K x r being V_r^T column-major (no transposed operand)
         BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_none, r, rows,
-                               K, &one, c->Vr, r, M, ld, &zero, Mout, ldo));
+                               K, &one, w.Vr, r, M, ld, &zero, Mout, ldo));
     }
     return CAKF_OK;
 }
@@ -774,14 +795,13 @@ extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
     if (!c) return CAKF_E_ARG;
     const int K = c->rank;
     if (K <= c->r) return CAKF_OK;
-    int rc = truncate_factor(c, c->M[c->cur], c->N, c->ldM, K, c->r, c->M[1 - c->cur], c->ldM,
-                             rotation);
+    int rc = truncate_factor(c, context_work(c), c->M[c->cur], c->N, c->ldM, K, c->r,
+                             c->M[1 - c->cur], c->ldM, rotation);
     if (rc) return rc;
     c->cur = 1 - c->cur;
     c->rank = c->r;
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
-
 
 // ------------------------------------------------------- log-likelihood derivative
 extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, double dt,
@@ -1025,7 +1045,8 @@ extern "C" int cakf_smooth_step(cakf_ctx* c, const cakf_smooth_input* in, float*
                            c->ldWs, st);
     const int K = i + rs;
     if (K > c->r) {
-        int rc = truncate_factor(c, Wn, c->n, c->ldWs, K, c->r, Ws, c->ldWs, nullptr);
+        int rc = truncate_factor(c, context_work(c), Wn, c->n, c->ldWs, K, c->r, Ws, c->ldWs,
+                                 nullptr);
         if (rc) return rc;
         c->sm_rank = c->r;          // result landed in the current buffer
     } else {
@@ -1253,6 +1274,11 @@ extern "C" int cakf_profile_read(cakf_ctx* c, double* total_ms, int* launches) {
         if (c->prof.on) c->prof.count[p] = c->prof.seen[p] = 0;
     }
     return CAKF_OK;
+}
+
+extern "C" int cakf_profile_rates(double* lanes_per_s) {
+    if (!lanes_per_s) return CAKF_E_ARG;
+    return probe_rates(lanes_per_s) == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 
 extern "C" int cakf_marginal_var(cakf_ctx* c, const int32_t* rows, int count, float* out) {

@@ -200,14 +200,20 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const double* __restrict
         d[K - 1] = failed ? __builtin_nan("") : Al[((K - 1) / NWG) * K + K - 1];
 }
 
+// Zero the barrier counter and the abort flag before a launch (a kernel rather than a
+// memset node, so that a captured stream replays it correctly).
+__global__ void k_clear_barrier(unsigned* ctr, int* abort_flag) {
+    *ctr = 0u;
+    *abort_flag = 0;
+}
+
 // Returns hipSuccess or the launch error (e.g. when the grid cannot be co-resident).
 hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double* d, double* e,
                           double* pbuf, double* rowbuf, unsigned* ctr, int* abort_flag,
                           hipStream_t st) {
     if (K < 3 || K > TD_MAXK) return hipErrorInvalidValue;
-    hipError_t err = hipMemsetAsync(ctr, 0, sizeof(unsigned), st);
-    if (err != hipSuccess) return err;
-    err = hipMemsetAsync(abort_flag, 0, sizeof(int), st);
+    hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(1), 0, st, ctr, abort_flag);
+    hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int nwg = tridiag_workgroups(K);
     void* args[] = {(void*)&G, (void*)&K, (void*)&V, (void*)&tau, (void*)&d, (void*)&e,

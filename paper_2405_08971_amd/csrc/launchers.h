@@ -148,6 +148,10 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
 void launch_backtransform(const double* Z, const double* Vh, const double* tau, int K, int r,
                           float* Vr, double* rot, hipStream_t st);
 
+// ---- probe.hip
+// lane operations per second of v_exp_f32, v_sqrt_f32 and v_fma_f32 (out: 3 doubles)
+hipError_t probe_rates(double* out);
+
 // ---- adjoint.hip
 // launch shape of k_adj_tiles: gx blocks of 32 q-points x gy slices of rps p-points
 void adj_tiles_geometry(int np_, int mq, int* gx, int* gy, int* rps);
