@@ -289,12 +289,15 @@ class StepRecord:
 
 def run_filter(model: Model, steps, max_actions: int, r_cap: int, policy: str = "cg",
                actions=None, resid_tol: float = 0.0, pivot_tol: float = 1e-10,
-               form: str = "iterative", rotations=None, m0=None, M0=None) -> List[StepRecord]:
+               form: str = "iterative", rotations=None, m0=None, M0=None,
+               lsqrt: str = "eigh") -> List[StepRecord]:
     """Alg. 1.  steps[k-1] = (idx_k, y_k) or None (no data) for k = 1..T.
 
     policy "cg": residual actions; policy ("block", b): block-residual actions in rounds
     of b; policy "given": actions[k-1] is S_k (m_k x i).
-    rotations[k-1], if given, replays the truncation rotation of step k."""
+    rotations[k-1], if given, replays the truncation rotation of step k.
+    form "batch" (given actions only) takes the square root lsqrt of update_batch; "chol"
+    gives the factor columns of the iterative form (S L^{-T})."""
     n = model.n
     m = np.zeros(n) if m0 is None else np.asarray(m0, np.float64)
     Mp = np.zeros((n, 0)) if M0 is None else np.asarray(M0, np.float64)
@@ -324,7 +327,8 @@ def run_filter(model: Model, steps, max_actions: int, r_cap: int, policy: str = 
                 if policy != "given":
                     raise ValueError("the batch form needs given actions")
                 res = update_batch(model, m_pred, M_pred, idx, y,
-                                   np.asarray(actions[k - 1], np.float64)[:, :max_actions])
+                                   np.asarray(actions[k - 1], np.float64)[:, :max_actions],
+                                   lsqrt=lsqrt)
             else:
                 raise ValueError(form)
             m, M = res.m, res.M

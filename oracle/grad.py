@@ -35,19 +35,23 @@ def model_at(base: Model, dt: float, theta: Sequence[float]) -> Model:
 
 
 def replay_loglik(base: Model, dt: float, theta, steps, recs: List[StepRecord],
-                  r_cap: int) -> float:
-    """Log-likelihood at theta with the actions and rotations of recs frozen."""
+                  r_cap: int, form: str = "iterative") -> float:
+    """Log-likelihood at theta with the actions and rotations of recs frozen.  form
+    "batch" replays with the batch update and the Cholesky square root (the same factor
+    columns S L^{-T} as the iterative form, App. B), which costs one projected-Gram
+    product per step instead of three per action."""
     model = model_at(base, dt, theta)
     actions = [None if r.S is None else r.S for r in recs]
     rotations = [r.V_r for r in recs]
     max_i = max([0] + [r.i_eff for r in recs])
     out = run_filter(model, steps, max_actions=max_i, r_cap=r_cap, policy="given",
-                     actions=actions, pivot_tol=-np.inf, rotations=rotations)
+                     actions=actions, pivot_tol=-np.inf, rotations=rotations, form=form,
+                     lsqrt="chol")
     return total_loglik(out)
 
 
 def fd_gradient(base: Model, dt: float, theta, steps, recs, r_cap: int,
-                rel_step: float = 1e-5) -> np.ndarray:
+                rel_step: float = 1e-5, form: str = "iterative") -> np.ndarray:
     """Central differences of replay_loglik in each parameter (relative step)."""
     theta = np.asarray(theta, np.float64)
     g = np.zeros(theta.size)
@@ -57,6 +61,6 @@ def fd_gradient(base: Model, dt: float, theta, steps, recs, r_cap: int,
         tm = theta.copy()
         tp[j] += h
         tm[j] -= h
-        g[j] = (replay_loglik(base, dt, tp, steps, recs, r_cap)
-                - replay_loglik(base, dt, tm, steps, recs, r_cap)) / (2.0 * h)
+        g[j] = (replay_loglik(base, dt, tp, steps, recs, r_cap, form)
+                - replay_loglik(base, dt, tm, steps, recs, r_cap, form)) / (2.0 * h)
     return g

@@ -111,3 +111,24 @@ def test_replay_reproduces_base_run_with_truncation():
     recs = run_filter(base, steps, 3, 4, policy="cg")
     ll = sum(r.loglik for r in recs)
     assert replay_loglik(base, dt, theta, steps, recs, 4) == pytest.approx(ll, abs=1e-10)
+
+
+def test_batch_replay_with_frozen_rotations_equals_the_iterative_replay():
+    """With truncation in the replay, the frozen rotation acts on the factor's columns, so
+    the replayed function depends on the square root of the projected Gram matrix: the
+    batch form with the Cholesky root gives the columns S L^{-T} of the iterative form
+    (App. B) and hence the same function and derivative; an eigen-decomposition root
+    (another basis of the same span) would not."""
+    model, steps = tiny_problem(seed=37, T=4, m=9)
+    rng = np.random.default_rng(38)
+    actions = [rng.standard_normal((9, 3)) for _ in steps]
+    dt, theta = 1.0, (0.3, 5.0, 1.3, 0.05)
+    base = model_at(model, dt, theta)
+    recs = run_filter(base, steps, 3, 4, policy="given", actions=actions)
+    assert sum(r.V_r is not None for r in recs) >= 2
+    for th in (theta, (0.31, 4.9, 1.25, 0.06)):
+        assert replay_loglik(base, dt, th, steps, recs, 4, form="batch") == pytest.approx(
+            replay_loglik(base, dt, th, steps, recs, 4), abs=1e-10)
+    g_it = fd_gradient(base, dt, theta, steps, recs, 4)
+    g_b = fd_gradient(base, dt, theta, steps, recs, 4, form="batch")
+    np.testing.assert_allclose(g_b, g_it, rtol=1e-7, atol=1e-9)
