@@ -44,6 +44,7 @@ typedef struct cakf_ctx cakf_ctx;
 #define CAKF_E_NOMEM  -3   /* device allocation failed in cakf_create                  */
 #define CAKF_E_STATE  -4   /* call out of order (e.g. truncate with nothing to drop)   */
 #define CAKF_E_SOLVER -5   /* rocBLAS / rocSOLVER returned an error                    */
+#define CAKF_E_SCRATCH -6  /* the call needs more than the static scratch array holds  */
 
 /* Spatial Matern kernel, identified by 2*nu. */
 #define CAKF_MATERN12 1
@@ -320,6 +321,27 @@ typedef struct {
 int cakf_sample_forward(cakf_ctx* ctx, int ns, const float* x_prev, const float* q,
                         const float* e, const cakf_sample_input* in, float* x_out,
                         float* w_obs_out);
+
+/* Forward step k as cakf_sample_forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * step's workspace is a file-scope device array of CAKF_STATIC_SCRATCH_BYTES (32 MiB) that
+ * each GPU the library runs on holds until the process ends, instead of the context's
+ * sampler workspace, so the context may be created with sample_paths = 0.  The call makes
+ * no device allocation and no library call that allocates; buffers it must start from
+ * zero are cleared by a kernel.  Same arguments, same kernels and the same results as
+ * cakf_sample_forward; ns <= CAKF_STATIC_MAX_PATHS.  The layout needs
+ * 4 bsp (3 mp + 2 imax + n) + 16 mp bytes, plus 4 bsp (n + pred_rank) when pred_rank > 0
+ * (bsp = ns rounded up to 32, mp = m rounded up to 128, imax = max_actions, each segment
+ * rounded up to 256 bytes); what is left holds the partial products of a block product
+ * split along the observations.  A call that needs more returns CAKF_E_SCRATCH before
+ * anything is enqueued.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (several streams or host threads) race
+ * and must be serialised by the caller. */
+#define CAKF_STATIC_SCRATCH_BYTES (32u << 20)
+#define CAKF_STATIC_MAX_PATHS 256
+int cakf_sample_forward_static(cakf_ctx* ctx, int ns, const float* x_prev, const float* q,
+                               const float* e, const cakf_sample_input* in, float* x_out,
+                               float* w_obs_out);
 
 /* ws_out (n x ns) = H^T w_obs: the last step's message, ws_T = w_T (zeros when m = 0). */
 int cakf_sample_lift(cakf_ctx* ctx, int ns, const int32_t* idx, const float* w_obs, int m,

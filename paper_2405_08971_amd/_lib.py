@@ -15,6 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcakf.so")
 
 CAKF_OK, CAKF_E_ARG, CAKF_E_HIP, CAKF_E_NOMEM, CAKF_E_STATE, CAKF_E_SOLVER = 0, -1, -2, -3, -4, -5
+CAKF_E_SCRATCH = -6
+CAKF_STATIC_SCRATCH_BYTES = 32 << 20
+CAKF_STATIC_MAX_PATHS = 256
 MATERN = {1: 1, 3: 3, 5: 5}
 DIST = {"euclid": 0, "geodesic": 1}
 PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
@@ -24,7 +27,8 @@ PHASES = ("sym_tiles", "form_u", "tail", "next_action", "block_product", "gram",
           "rotate", "predict", "update", "truncate")
 _ERR = {CAKF_E_ARG: "invalid argument", CAKF_E_HIP: "HIP runtime error",
         CAKF_E_NOMEM: "device allocation failed", CAKF_E_STATE: "call out of order",
-        CAKF_E_SOLVER: "rocBLAS/rocSOLVER error"}
+        CAKF_E_SOLVER: "rocBLAS/rocSOLVER error",
+        CAKF_E_SCRATCH: "the call needs more than the static scratch array holds"}
 
 
 class cakf_config(ctypes.Structure):
@@ -116,6 +120,8 @@ def lib() -> ctypes.CDLL:
                                      i, vp, ctypes.POINTER(i)]),
             "cakf_sample_forward": (i, [vp, i, vp, vp, vp, ctypes.POINTER(cakf_sample_input),
                                         vp, vp]),
+            "cakf_sample_forward_static": (i, [vp, i, vp, vp, vp,
+                                               ctypes.POINTER(cakf_sample_input), vp, vp]),
             "cakf_sample_lift": (i, [vp, i, vp, vp, i, vp]),
             "cakf_sample_backward": (i, [vp, i, vp, vp, i, i,
                                          ctypes.POINTER(cakf_sample_input), vp, vp, vp, vp]),
@@ -263,6 +269,13 @@ def cakf_sample_forward(ctx: int, ns: int, x_prev, q, e, inp: cakf_sample_input,
                         w_obs_out) -> None:
     check(lib().cakf_sample_forward(ctx, ns, ptr(x_prev), ptr(q), ptr(e), ctypes.byref(inp),
                                     ptr(x_out), ptr(w_obs_out)), "cakf_sample_forward")
+
+
+def cakf_sample_forward_static(ctx: int, ns: int, x_prev, q, e, inp: cakf_sample_input,
+                               x_out, w_obs_out) -> None:
+    check(lib().cakf_sample_forward_static(ctx, ns, ptr(x_prev), ptr(q), ptr(e),
+                                           ctypes.byref(inp), ptr(x_out), ptr(w_obs_out)),
+          "cakf_sample_forward_static")
 
 
 def cakf_sample_lift(ctx: int, ns: int, idx, w_obs, m: int, ws_out) -> None:

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <vector>
+#include <mutex>
 #include <new>
 
 #include "../../include/cakf.h"
@@ -255,6 +256,59 @@ static int validate(const cakf_config* c) {
     return CAKF_OK;
 }
 
+// ------------------------------------------------------- static scratch (no allocation)
+// The workspace of cakf_sample_forward_static: a file-scope device array of
+// CAKF_STATIC_SCRATCH_BYTES, one copy per GPU, held until the process ends.  In host code
+// the array's name is not a device address: the address of the current device's copy is
+// looked up once per device (cakf_create, with that device current) and only that address
+// is handed to kernels and library calls.
+static __device__ __align__(256) unsigned char scratch[CAKF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_addr[SCRATCH_MAX_DEVICES];
+bool scratch_looked_up[SCRATCH_MAX_DEVICES];
+
+// Device address of this device's scratch copy (dev must be the current device).
+void scratch_lookup(int dev) {
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> guard(scratch_mu);
+    if (scratch_looked_up[dev]) return;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) {
+        scratch_addr[dev] = p;
+        scratch_looked_up[dev] = true;
+    } else {
+        (void)hipGetLastError();   // leave no error behind for later calls
+    }
+}
+
+void* scratch_of(int dev) {
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> guard(scratch_mu);
+    return scratch_addr[dev];
+}
+
+// Bump allocation of 256-byte aligned segments inside [base, base + cap).
+struct Carve {
+    char* base;
+    size_t cap, used = 0;
+    bool ok = true;
+    template <typename Tp>
+    Tp* take(size_t count) {
+        const size_t bytes = (count * sizeof(Tp) + 255) / 256 * 256;
+        if (!ok || bytes > cap - used) {
+            ok = false;
+            return nullptr;
+        }
+        Tp* p = reinterpret_cast<Tp*>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+}  // namespace
+
 extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     if (!out) return CAKF_E_ARG;
     *out = nullptr;
@@ -270,6 +324,8 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         delete c;
         return CAKF_E_HIP;
     }
+    // the static scratch array's address on this device (cakf_sample_forward_static)
+    scratch_lookup(c->device);
     c->n = cfg->n;
     c->N = cfg->temporal == CAKF_TEMPORAL_MATERN32 ? 2 * cfg->n : cfg->n;
     c->r = cfg->max_rank;
@@ -1115,44 +1171,107 @@ static int sample_input_ok(const cakf_ctx* c, const cakf_sample_input* in, bool 
     return 1;
 }
 
-extern "C" int cakf_sample_forward(cakf_ctx* c, int ns, const float* x_prev, const float* q,
-                                   const float* e, const cakf_sample_input* in, float* x_out,
-                                   float* w_obs_out) {
-    if (!c || !c->sp_B || ns < 1 || ns > c->sp_ns || !x_prev || !q || !x_out) return CAKF_E_ARG;
-    if (!sample_input_ok(c, in, true)) return CAKF_E_ARG;
-    if (in->m > 0 && (!e || !w_obs_out)) return CAKF_E_ARG;
+// Workspace of one forward sampler step (sizes for bsp = ns rounded to 32 columns).
+struct SampleWork {
+    float *B, *W, *Y, *D, *R, *Z, *Q;
+    __bf16 *Bth, *Btl;
+    float4* Xo;
+    float* part;            // partial products of an observation-split block product
+    size_t part_elems;
+};
+
+// Forward step of the sampler on the workspace w: x^- = a x_{k-1} + q, then
+// x = x^- + P^- H^T W_obs L^{-1} S^T (y - x^-[idx] - sigma e).  Padding rows of the
+// block-product operand are cleared by a kernel (no memset node), so the same sequence
+// serves the static-scratch entry point.
+static int sample_forward_impl(cakf_ctx* c, int ns, const float* x_prev, const float* q,
+                               const float* e, const cakf_sample_input* in, float* x_out,
+                               float* w_obs_out, const SampleWork& w) {
     hipStream_t st = c->stream;
-    const int n = c->n, m = in->m, imax = c->imax, bsp = c->bsp;
+    const int n = c->n, m = in->m, imax = c->imax, bsp = round_up(ns, 32);
     // x^- = a x_{k-1} + q
     launch_sample_predict(x_prev, q, (float)c->cfg.ou_coeff, n, ns, ns, x_out, st);
     if (m == 0) return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
     const int mp = round_up(m, SYM_TILE);
     // d = y - x^-[idx] - sigma e;  z = L^{-1} S^T d;  wobs = W_obs z (zero padding rows)
     launch_sample_innov(in->y, in->idx, x_out, ns, e, ns, (float)std::sqrt(c->cfg.noise_var), n,
-                        m, ns, c->sp_D, bsp, st);
-    BLAS_TRY(sgemm_rm(c->blas, true, false, imax, ns, m, 1.0f, in->S, imax, c->sp_D, bsp, 0.0f,
-                      c->sp_R, bsp));
-    launch_sample_solve(in->chol_inv, imax, c->sp_R, ns, bsp, c->sp_Z, st);
-    HIP_TRY(hipMemsetAsync(c->sp_B, 0, (size_t)mp * bsp * sizeof(float), st));
-    BLAS_TRY(sgemm_rm(c->blas, false, false, m, ns, imax, 1.0f, in->W_obs, imax, c->sp_Z, bsp,
-                      0.0f, c->sp_B, bsp));
-    launch_copy_rows(c->sp_B, bsp, w_obs_out, ns, m, ns, st);
+                        m, ns, w.D, bsp, st);
+    BLAS_TRY(sgemm_rm(c->blas, true, false, imax, ns, m, 1.0f, in->S, imax, w.D, bsp, 0.0f,
+                      w.R, bsp));
+    launch_sample_solve(in->chol_inv, imax, w.R, ns, bsp, w.Z, st);
+    launch_fill_zero(w.B, (size_t)mp * bsp, st);
+    BLAS_TRY(sgemm_rm(c->blas, false, false, m, ns, imax, 1.0f, in->W_obs, imax, w.Z, bsp,
+                      0.0f, w.B, bsp));
+    launch_copy_rows(w.B, bsp, w_obs_out, ns, m, ns, st);
     // x = x^- + sigma_f2 K(X, Xo) wobs - M^- (M^-^T H^T wobs)
-    launch_gather_points(c->Xs, n, in->idx, m, mp, c->sp_Xo, st);
-    launch_block_product(c->cfg.kernel, c->cfg.dist, c->cfg.prec, c->Xs, n, c->sp_Xo, m, mp,
-                         c->sp_B, bsp, ns, c->sp_Bth, c->sp_Btl, (float)c->cfg.signal_var,
-                         c->sp_Y, bsp, st, block_product_splits(n, mp, ns, c->bpart_elems),
-                         c->bpart);
-    launch_add_cols(c->sp_Y, bsp, n, ns, x_out, ns, st);
+    launch_gather_points(c->Xs, n, in->idx, m, mp, w.Xo, st);
+    launch_block_product(c->cfg.kernel, c->cfg.dist, c->cfg.prec, c->Xs, n, w.Xo, m, mp,
+                         w.B, bsp, ns, w.Bth, w.Btl, (float)c->cfg.signal_var,
+                         w.Y, bsp, st, block_product_splits(n, mp, ns, w.part_elems), w.part);
+    launch_add_cols(w.Y, bsp, n, ns, x_out, ns, st);
     if (in->pred_rank > 0) {
-        HIP_TRY(hipMemsetAsync(c->sp_W, 0, (size_t)n * bsp * sizeof(float), st));
-        launch_sample_scatter(in->idx, n, m, ns, c->sp_B, bsp, nullptr, 0, c->sp_W, bsp, st);
+        launch_fill_zero(w.W, (size_t)n * bsp, st);
+        launch_sample_scatter(in->idx, n, m, ns, w.B, bsp, nullptr, 0, w.W, bsp, st);
         BLAS_TRY(sgemm_rm(c->blas, true, false, in->pred_rank, ns, n, 1.0f, in->pred_factor,
-                          in->pred_ld, c->sp_W, bsp, 0.0f, c->sp_Q, bsp));
+                          in->pred_ld, w.W, bsp, 0.0f, w.Q, bsp));
         BLAS_TRY(sgemm_rm(c->blas, false, false, n, ns, in->pred_rank, -1.0f, in->pred_factor,
-                          in->pred_ld, c->sp_Q, bsp, 1.0f, x_out, ns));
+                          in->pred_ld, w.Q, bsp, 1.0f, x_out, ns));
     }
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
+}
+
+static int sample_forward_args_ok(const cakf_ctx* c, int ns, const float* x_prev,
+                                  const float* q, const float* e, const cakf_sample_input* in,
+                                  const float* x_out, const float* w_obs_out) {
+    if (!c || ns < 1 || !x_prev || !q || !x_out) return 0;
+    if (!sample_input_ok(c, in, true)) return 0;
+    if (in->m > 0 && (!e || !w_obs_out)) return 0;
+    return 1;
+}
+
+extern "C" int cakf_sample_forward(cakf_ctx* c, int ns, const float* x_prev, const float* q,
+                                   const float* e, const cakf_sample_input* in, float* x_out,
+                                   float* w_obs_out) {
+    if (!sample_forward_args_ok(c, ns, x_prev, q, e, in, x_out, w_obs_out)) return CAKF_E_ARG;
+    if (!c->sp_B || ns > c->sp_ns) return CAKF_E_ARG;
+    SampleWork w{c->sp_B, c->sp_W, c->sp_Y, c->sp_D, c->sp_R, c->sp_Z, c->sp_Q,
+                 c->sp_Bth, c->sp_Btl, c->sp_Xo, c->bpart, c->bpart_elems};
+    return sample_forward_impl(c, ns, x_prev, q, e, in, x_out, w_obs_out, w);
+}
+
+extern "C" int cakf_sample_forward_static(cakf_ctx* c, int ns, const float* x_prev,
+                                          const float* q, const float* e,
+                                          const cakf_sample_input* in, float* x_out,
+                                          float* w_obs_out) {
+    if (!sample_forward_args_ok(c, ns, x_prev, q, e, in, x_out, w_obs_out)) return CAKF_E_ARG;
+    if (ns > CAKF_STATIC_MAX_PATHS) return CAKF_E_ARG;
+    void* base = scratch_of(c->device);
+    if (!base) return CAKF_E_HIP;
+    SampleWork w{};
+    if (in->m > 0) {
+        // the layout is checked against the array's size before anything is enqueued
+        const size_t bsp = round_up(ns, 32), mp = round_up(in->m, SYM_TILE), n = c->n;
+        Carve cv{static_cast<char*>(base), CAKF_STATIC_SCRATCH_BYTES};
+        w.D = cv.take<float>(mp * bsp);
+        w.R = cv.take<float>((size_t)c->imax * bsp);
+        w.Z = cv.take<float>((size_t)c->imax * bsp);
+        w.B = cv.take<float>(mp * bsp);
+        w.Xo = cv.take<float4>(mp);
+        w.Bth = cv.take<__bf16>(mp * bsp);
+        w.Btl = cv.take<__bf16>(mp * bsp);
+        w.Y = cv.take<float>(n * bsp);
+        if (in->pred_rank > 0) {
+            w.W = cv.take<float>(n * bsp);
+            w.Q = cv.take<float>((size_t)in->pred_rank * bsp);
+        }
+        if (!cv.ok) return CAKF_E_SCRATCH;
+        // what is left holds the partial products of an observation-split block product,
+        // capped as in a context's workspace
+        const size_t left = (cv.cap - cv.used) / sizeof(float);
+        w.part_elems = std::min(left, (size_t)32 << 20);
+        w.part = w.part_elems ? cv.take<float>(w.part_elems) : nullptr;
+    }
+    return sample_forward_impl(c, ns, x_prev, q, e, in, x_out, w_obs_out, w);
 }
 
 extern "C" int cakf_sample_lift(cakf_ctx* c, int ns, const int32_t* idx, const float* w_obs,

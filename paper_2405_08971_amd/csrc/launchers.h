@@ -35,6 +35,7 @@ void launch_mean_add(float* mean, const float* M, int n, int ld, int col, hipStr
 void launch_predict_pairs(float* mean, float* M, int n, int ld, int rank, const float t[4],
                           hipStream_t st);
 void launch_zero_cols(float* M, int ld, int rows, int cols, hipStream_t st);
+void launch_fill_zero(float* p, size_t count, hipStream_t st);
 void launch_marginal_var(const float* M, int n, int ld, int rank, float sigma_f2,
                          const int32_t* rows, int count, float* out, hipStream_t st);
 void launch_copy_rows(const float* src, int lds, float* dst, int ldd, int rows, int cols,

@@ -88,6 +88,19 @@ void launch_zero_cols(float* M, int ld, int rows, int cols, hipStream_t st) {
                        dim3(256), 0, st, M, ld, rows, cols);
 }
 
+// p[e] = 0 for e < count: clears workspace with a kernel rather than a memset node.
+__global__ void k_fill_zero(float* __restrict__ p, size_t count) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (size_t)gridDim.x * blockDim.x)
+        p[e] = 0.0f;
+}
+
+void launch_fill_zero(float* p, size_t count, hipStream_t st) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_fill_zero, dim3((int)std::min<size_t>((count + 255) / 256, 8192)),
+                       dim3(256), 0, st, p, count);
+}
+
 // m <- m + M[:, col]  (the mean column of the block product).
 __global__ void k_mean_add(float* __restrict__ mean, const float* __restrict__ M, int n, int ld,
                            int col) {

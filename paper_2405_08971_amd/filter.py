@@ -198,16 +198,24 @@ class CAKF:
             pred_factor=L.ptr(pred_factor) if pr else None, pred_ld=max(pr, 1), pred_rank=pr)
 
     def sample_forward(self, x_prev: torch.Tensor, q: torch.Tensor, e: Optional[torch.Tensor],
-                       idx, y, record: Optional[Record], pred_factor: torch.Tensor):
+                       idx, y, record: Optional[Record], pred_factor: torch.Tensor,
+                       static_scratch: bool = False, out=None):
         """Forward step of the path sampler: returns (x_k, w_obs_k) for the ns paths in the
-        columns of x_prev (n x ns); q (n x ns) and e (m x ns) are the step's draws."""
+        columns of x_prev (n x ns); q (n x ns) and e (m x ns) are the step's draws.
+        static_scratch: run on the library's static scratch array
+        (cakf_sample_forward_static, which allocates nothing); out: optional preallocated
+        (x, w) with w of at least max(m, 1) rows."""
         ns = x_prev.shape[1]
         m = 0 if idx is None else int(idx.numel())
         inp = self._sample_input(idx, y, record, pred_factor)
-        x = torch.empty_like(x_prev)
-        w = torch.empty((max(m, 1), ns), dtype=torch.float32, device="cuda")
-        L.cakf_sample_forward(self.ctx, ns, x_prev.contiguous(), q.contiguous(),
-                              e.contiguous() if m else None, inp, x, w if m else None)
+        if out is None:
+            x = torch.empty_like(x_prev)
+            w = torch.empty((max(m, 1), ns), dtype=torch.float32, device="cuda")
+        else:
+            x, w = out
+        fn = L.cakf_sample_forward_static if static_scratch else L.cakf_sample_forward
+        fn(self.ctx, ns, x_prev.contiguous(), q.contiguous(), e.contiguous() if m else None, inp,
+           x, w if m else None)
         return x, w[:m]
 
     def sample_lift(self, idx, w_obs: torch.Tensor, ns: int) -> torch.Tensor:
