@@ -377,21 +377,29 @@ def vs_fp64_reference(cfg, X, wl, prec):
 
 
 def precision_replay(cfg, X, wl, T, keep=2):
-    """The headline mode with CG actions and, in lockstep, the FP32-plain path replaying
-    those actions, over T steps (untimed).  CG actions depend on every rounding before
-    them, so two free runs are not comparable; with the actions shared the difference is
-    due to arithmetic precision alone.  Per step: relative mean difference of the mean and
-    of the marginal variance on the 2048-point subset; the maximum over steps is reported.
-    The first `keep` steps' actions and subset results of both runs are returned for the
-    FP64 replay of the CPU-baseline leg."""
+    """Precision over the whole run, untimed.  CG actions depend on every rounding before
+    them, so two free runs are not comparable.  A headline-mode CG run (a) supplies the
+    action sequence; the FP32-plain path (b) and the headline mode (c) both replay it
+    through the given-action path, in lockstep.  Per step, on the 2048-point subset, the
+    relative mean difference of the mean and the marginal variance:
+      b vs c  - arithmetic precision alone (same actions, same code path);
+      a vs c  - same precision, the CG path against the given-action path (they differ
+                only in the summation order of Mo^T S): the floor that rounding order alone
+                sets on this workload.
+    The maximum over steps and the last step are reported.  The first `keep` steps of a
+    and of an FP32-plain CG run (d) return their actions and subset results for the FP64
+    oracle replay of the CPU-baseline leg."""
     import torch
     from paper_2405_08971_amd.filter import Record
     sub = wl.subset(2048)
     rows = torch.from_numpy(sub.astype(np.int32)).cuda()
     fa = make_filter(cfg, X, "bf16x3", policy="cg")
     fb = make_filter(cfg, X, "fp32", policy="given")
-    worst = {"mean": 0.0, "var": 0.0, "mean_step": 0, "var_step": 0}
-    kept = []
+    fc = make_filter(cfg, X, "bf16x3", policy="given")
+    fd = make_filter(cfg, X, "fp32", policy="cg")
+    pairs = {"bf16x3_vs_fp32_same_actions": (2, 1), "cg_vs_given_path_bf16x3": (0, 2)}
+    worst = {name: {"mean": 0.0, "var": 0.0, "mean_step": 0, "var_step": 0} for name in pairs}
+    kept = {"bf16x3": [], "fp32": []}
     for k in range(1, T + 1):
         idx, y = wl.step(k)
         idx_d = torch.from_numpy(idx.astype(np.int32)).cuda()
@@ -399,29 +407,40 @@ def precision_replay(cfg, X, wl, T, keep=2):
         rec = Record(cfg.m, cfg.i)
         fa.step(idx_d, y_d, record=rec)
         fb.step(idx_d, y_d, rec.S)
-        ma, va = fa.state()[0][rows.long()].cpu().numpy(), fa.marginal_var(rows).cpu().numpy()
-        mb, vb = fb.state()[0][rows.long()].cpu().numpy(), fb.marginal_var(rows).cpu().numpy()
-        for key, x, r in (("mean", ma, mb), ("var", va, vb)):
-            e = err_fields(x, r)[0]
-            if e > worst[key]:
-                worst[key], worst[key + "_step"] = e, k
+        fc.step(idx_d, y_d, rec.S)
+        res = [(f.state()[0][rows.long()].cpu().numpy(), f.marginal_var(rows).cpu().numpy())
+               for f in (fa, fb, fc)]
+        for name, (u, v) in pairs.items():
+            for key, col in (("mean", 0), ("var", 1)):
+                e = err_fields(res[u][col], res[v][col])[0]
+                if e > worst[name][key]:
+                    worst[name][key], worst[name][key + "_step"] = e, k
         if k <= keep:
             na = int(rec.n_actions.item())
-            kept.append(dict(idx=idx, y=y, S=rec.S.cpu().numpy()[:, :na],
-                             bf16x3=(ma, va), fp32=(mb, vb)))
-    worst["final"] = {"mean": err_fields(ma, mb)[0], "var": err_fields(va, vb)[0]}
-    worst["steps"] = T
-    fa.close()
-    fb.close()
+            kept["bf16x3"].append(dict(idx=idx, y=y, S=rec.S.cpu().numpy()[:, :na],
+                                       mean=res[0][0], var=res[0][1]))
+            rd = Record(cfg.m, cfg.i)
+            fd.step(idx_d, y_d, record=rd)
+            nd = int(rd.n_actions.item())
+            kept["fp32"].append(dict(idx=idx, y=y, S=rd.S.cpu().numpy()[:, :nd],
+                                     mean=fd.state()[0][rows.long()].cpu().numpy(),
+                                     var=fd.marginal_var(rows).cpu().numpy()))
+    for name, (u, v) in pairs.items():
+        worst[name]["final"] = {key: err_fields(res[u][col], res[v][col])[0]
+                                for key, col in (("mean", 0), ("var", 1))}
+        worst[name]["steps"] = T
+    for f in (fa, fb, fc, fd):
+        f.close()
     return worst, kept
 
 
 def cpu_baseline(cfg, wl, kept):
     """The FP64 oracle timed on the host cores on a bounded sample of the same workload:
-    the first len(kept) steps, with the batch update of Alg. 2 conditioning on the actions
-    the GPU's CG run took (the oracle's form for given actions) and the truncation of
-    Sec. 3.2.  Seconds per step are measured, not extrapolated.  The same run gives the
-    FP64 error of the GPU's CG steps (both modes) on the 2048-point subset."""
+    the first steps, with the batch update of Alg. 2 conditioning on the actions a GPU CG
+    run took (the oracle's form for given actions) and the truncation of Sec. 3.2, once
+    for the headline mode's actions and once for the FP32-plain path's.  Seconds per step
+    are measured, not extrapolated.  The same runs give each mode's FP64 error on its own
+    CG steps on the 2048-point subset."""
     from oracle.cakf import Model, run_filter
     threads = max(1, min(16, os.cpu_count() or 1))
     os.environ["ORACLE_THREADS"] = str(threads)
@@ -432,36 +451,38 @@ def cpu_baseline(cfg, wl, kept):
         limit = None
     X = wl.X.astype(np.float32).astype(np.float64)
     model = Model(X, cfg.nu2, cfg.ell, cfg.sigma_f2, cfg.a, cfg.noise_var, cfg.dist)
-    steps = [(s["idx"].astype(np.int64), s["y"].astype(np.float32).astype(np.float64))
-             for s in kept]
-    acts = [s["S"].astype(np.float64) for s in kept]
-    t0 = time.perf_counter()
-    recs = run_filter(model, steps, cfg.i, cfg.r, policy="given", actions=acts, form="batch")
-    elapsed = time.perf_counter() - t0
-    if limit is not None:
-        limit.restore_original_limits()
     sub = wl.subset(2048)
-    err = {}
-    for prec in ("bf16x3", "fp32"):
+    err, elapsed, nsteps = {}, 0.0, 0
+    for prec, runs in kept.items():
+        steps = [(s["idx"].astype(np.int64), s["y"].astype(np.float32).astype(np.float64))
+                 for s in runs]
+        acts = [s["S"].astype(np.float64) for s in runs]
+        t0 = time.perf_counter()
+        recs = run_filter(model, steps, cfg.i, cfg.r, policy="given", actions=acts,
+                          form="batch")
+        elapsed += time.perf_counter() - t0
+        nsteps += len(runs)
         e = {}
-        for k, (s, rec) in enumerate(zip(kept, recs)):
-            for key, x, r in (("mean", s[prec][0], rec.m[sub]),
-                              ("var", s[prec][1],
+        for s, rec in zip(runs, recs):
+            for key, x, r in (("mean", s["mean"], rec.m[sub]),
+                              ("var", s["var"],
                                cfg.sigma_f2 - np.sum(rec.M_plus[sub] ** 2, axis=1))):
                 em, ex = err_fields(x, r)
                 e[key] = max(e.get(key, 0.0), em)
                 e[key + "_max"] = max(e.get(key + "_max", 0.0), ex)
         err[prec] = e
+    if limit is not None:
+        limit.restore_original_limits()
     try:
         import platform
         model_name = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
                            if ln.startswith("model name")), platform.processor())
     except Exception:
         model_name = "unknown"
-    base = dict(value=len(kept) / elapsed, unit="steps/s", cores=threads, kind="oracle",
-                sample=(f"first {len(kept)} steps of {cfg.name} ({elapsed:.1f} s, "
-                        f"{elapsed / len(kept):.1f} s/step measured): the FP64 oracle's batch "
-                        f"update (Alg. 2) on the GPU run's CG actions, then its truncation; "
+    base = dict(value=nsteps / elapsed, unit="steps/s", cores=threads, kind="oracle",
+                sample=(f"first {nsteps // len(kept)} steps of {cfg.name}, twice ({elapsed:.1f} s, "
+                        f"{elapsed / nsteps:.1f} s/step measured): the FP64 oracle's batch "
+                        f"update (Alg. 2) on a GPU CG run's actions, then its truncation; "
                         f"kernel products over {threads} threads, BLAS {threads} threads; "
                         f"host: {model_name}"))
     return base, err
@@ -554,7 +575,8 @@ def main():
         for prec in ("bf16x3", "fp32"):
             acc[f"vs_fp64_given_actions_{prec}"] = vs_fp64_reference(cfg, X, wl, prec)
         T = min(args.replay_steps, cfg.T)
-        acc["bf16x3_vs_fp32_replay"], kept = precision_replay(cfg, X, wl, T)
+        replay, kept = precision_replay(cfg, X, wl, T)
+        acc.update(replay)
         line["accuracy"] = acc
     if not args.no_next_rows:
         line["next_rows"] = next_rows(args.seed)
@@ -587,8 +609,8 @@ def main():
     if not args.no_cpu_baseline and kept:
         line["cpu_baseline"], err = cpu_baseline(cfg, wl, kept)
         line["accuracy"]["vs_fp64_cg_actions"] = dict(
-            err, steps=len(kept), note="the FP64 oracle replaying the headline run's CG "
-                                       "actions (the FP32 path replays the same actions)")
+            err, steps=len(kept["bf16x3"]),
+            note="each mode's own CG run against the FP64 oracle replaying its actions")
     print(json.dumps(line), flush=True)
 
 

@@ -47,10 +47,13 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
                                                     const __bf16* __restrict__ Btl, int ldbt,
                                                     int tile0, int ncols, float sigma_f2,
                                                     float* __restrict__ out, int ldo,
-                                                    int qchunk, size_t part_stride) {
+                                                    int qchunk, size_t part_stride,
+                                                    const float* __restrict__ Bf, int ldbf,
+                                                    int fcol) {
     __shared__ float4 xo[MF_KC];
     __shared__ bf16x8 bh[NT * 32][MF_KC / 8 + 1];
     __shared__ bf16x8 bl[X3 ? NT * 32 : 1][MF_KC / 8 + 1];
+    __shared__ float wf[MF_KC];       // the FP32 column's chunk, in stored order
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rl = lane & 31, half = lane >> 5;
     const int row0 = blockIdx.x * MF_ROWS + w * 32;
@@ -63,12 +66,20 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
     for (int c = 0; c < NT; ++c)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[c][i] = 0.0f;
+    // column fcol (>= 0) is also summed in FP32 from the FP32 kernel entries, one chunk at a
+    // time, the chunk sums added in FP64; it replaces that column's MFMA result
+    const bool fp = fcol >= 0;
+    double fsum = 0.0;
     // observation range of this split (qchunk a multiple of MF_KC)
     const int qend = min(mp, (int)(blockIdx.y + 1) * qchunk);
     out += blockIdx.y * part_stride;
     for (int q0 = blockIdx.y * qchunk; q0 < qend; q0 += MF_KC) {
         __syncthreads();
         if (threadIdx.x < MF_KC) xo[threadIdx.x] = Xo[q0 + threadIdx.x];
+        if (fp && threadIdx.x >= 64 && threadIdx.x < 64 + MF_KC) {
+            const int q = q0 + threadIdx.x - 64;
+            wf[threadIdx.x - 64] = Bf[(size_t)(MD ? md_perm(q) : q) * ldbf + fcol];
+        }
         for (int e = threadIdx.x; e < NT * 32 * (MF_KC / 8); e += 256) {
             const int c = e / (MF_KC / 8), g = e % (MF_KC / 8);
             const size_t off = (size_t)(tile0 * 32 + c) * ldbt + q0 + 8 * g;
@@ -77,9 +88,11 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
         }
         __syncthreads();
         f32x16 dd;
+        float fchunk = 0.0f;
 #pragma unroll
         for (int ks = 0; ks < MF_KC / 16; ++ks) {
             bf16x8 ah, al;
+            float kv[8];
             if constexpr (MD) {
                 if (ks % 2 == 0) {
                     // squared distances of the 32 observations of k-steps ks, ks + 1
@@ -94,6 +107,7 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
                 for (int t = 0; t < 8; ++t) {
                     const float ka =
                         matern_u<NU2>(__builtin_amdgcn_sqrtf(__builtin_fabsf(dd[8 * (ks % 2) + t])));
+                    kv[t] = ka;
                     ah[t] = (__bf16)ka;
                     if constexpr (X3) al[t] = (__bf16)(ka - (float)ah[t]);
                 }
@@ -101,9 +115,16 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     const float ka = kval<NU2, DIST>(xa, xo[ks * 16 + 8 * half + t]);
+                    kv[t] = ka;
                     ah[t] = (__bf16)ka;
                     if constexpr (X3) al[t] = (__bf16)(ka - (float)ah[t]);
                 }
+            }
+            // the lane's 8 entries sit at stored positions ks * 16 + 8 half + t
+            if (fp) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    fchunk = __builtin_fmaf(kv[t], wf[ks * 16 + 8 * half + t], fchunk);
             }
             // the three products of each column tile are issued NT apart, so that no
             // MFMA waits on the result of the one before it
@@ -122,6 +143,7 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
                         ah, bl[c * 32 + rl][ks * 2 + half], acc[c], 0, 0, 0);
             }
         }
+        fsum += (double)fchunk;
     }
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
@@ -129,8 +151,16 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int row = row0 + 8 * (i / 4) + 4 * half + (i % 4);
-            if (row < n && col < ncols) out[(size_t)row * ldo + col] = sigma_f2 * acc[c][i];
+            if (row < n && col < ncols && col != fcol)
+                out[(size_t)row * ldo + col] = sigma_f2 * acc[c][i];
         }
+    }
+    if (fp) {
+        // the two half-waves hold the same row over complementary observations
+        const double other = __shfl_xor(fsum, 32, 64);
+        const double tot = half == 0 ? fsum + other : other + fsum;
+        if (half == 0 && row0 + rl < n)
+            out[(size_t)(row0 + rl) * ldo + fcol] = (float)((double)sigma_f2 * tot);
     }
 }
 
@@ -138,11 +168,13 @@ template <int NU2, int DIST, bool X3>
 static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const float4* Xo,
                               int mp, const __bf16* Bth, const __bf16* Btl, int ldbt,
                               int ncols, float sigma_f2, float* out, int ldo, int nsplit,
-                              int qchunk, size_t part_stride, hipStream_t st) {
+                              int qchunk, size_t part_stride, const float* Bf, int ldbf,
+                              int fcol, hipStream_t st) {
     const dim3 grid((n + MF_ROWS - 1) / MF_ROWS, nsplit), block(256);
 #define CAKF_MF(NTV)                                                                       \
     hipLaunchKernelGGL((k_block_mfma<NU2, DIST, NTV, X3>), grid, block, 0, st, Xs, n, Xo, mp, \
-                       Bth, Btl, ldbt, tile0, ncols, sigma_f2, out, ldo, qchunk, part_stride)
+                       Bth, Btl, ldbt, tile0, ncols, sigma_f2, out, ldo, qchunk, part_stride,  \
+                       Bf, ldbf, fcol)
     switch (nt) {
         case 1: CAKF_MF(1); break;
         case 2: CAKF_MF(2); break;
@@ -297,7 +329,7 @@ int block_product_splits(int n, int mp, int bcols, size_t part_elems) {
 void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
                           const float4* Xo, int m, int mp, const float* B, int ldb, int bcols,
                           __bf16* Bth, __bf16* Btl, float sigma_f2, float* out, int ldo,
-                          hipStream_t st, int nsplit, float* part) {
+                          hipStream_t st, int nsplit, float* part, int fp32_col) {
     // With nsplit > 1 the observation axis is cut into nsplit ranges (multiples of 512
     // observations), each range's product goes to part (n x bcols per range) and the ranges
     // are summed into out afterwards.
@@ -324,16 +356,19 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
                            (dist == DIST_EUCLID && nu2 != 1) ? 1 : 0, Bth, Btl);
         for (int t0 = 0; t0 < ntiles; t0 += 5) {
             const int nt = std::min(5, ntiles - t0);
+            // the FP32 column is summed by the launch whose tiles hold it
+            const int fc = (fp32_col >= 32 * t0 && fp32_col < std::min(32 * (t0 + nt), bcols))
+                               ? fp32_col : -1;
             if (prec == 2) {
                 CAKF_DISPATCH_KERNEL(nu2, dist,
                     (launch_mfma_tiles<NU2, DIST, true>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp,
                                                         bcols, sigma_f2, dst, ldd, nsplit,
-                                                        qchunk, stride, st)));
+                                                        qchunk, stride, B, ldb, fc, st)));
             } else {
                 CAKF_DISPATCH_KERNEL(nu2, dist,
                     (launch_mfma_tiles<NU2, DIST, false>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp,
                                                          bcols, sigma_f2, dst, ldd, nsplit,
-                                                         qchunk, stride, st)));
+                                                         qchunk, stride, B, ldb, fc, st)));
             }
         }
     }

@@ -763,9 +763,12 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     // Y = Sigma[:, idx] B into the new columns rank .. rank + b of the factor
     {
         PhaseTimer t(c, CAKF_PHASE_BLOCK_PRODUCT);
+        // the mean column w (column imax) is summed in FP32 in the BF16 modes: the mean
+        // increment is a small difference of the two parts of P^- H^T w
         launch_block_product(nu2, dist, c->cfg.prec, c->Xs, c->n, c->Xo, m, d.mp, c->B, c->bp, b,
                              c->Bth, c->Btl, (float)c->cfg.signal_var, M + d.rank, c->ldM, st,
-                             block_product_splits(c->n, d.mp, b, c->bpart_elems), c->bpart);
+                             block_product_splits(c->n, d.mp, b, c->bpart_elems), c->bpart,
+                             c->imax);
     }
     // the scaled-derivative rows of Sigma_inf H^T [W w] are zero (I_2 (x) Sigma)
     if (c->N > c->n) launch_zero_cols(M + (size_t)c->n * c->ldM + d.rank, c->ldM, c->N - c->n, b, st);
@@ -1038,7 +1041,8 @@ static int smooth_moments(cakf_ctx* c, const cakf_smooth_input* in, float g, flo
         launch_block_product(c->cfg.kernel, c->cfg.dist, c->cfg.prec, c->Xs, c->n, c->Xp, c->n,
                              c->np, c->sm_B, c->bps, b, c->sm_Bth, c->sm_Btl,
                              (float)c->cfg.signal_var, c->sm_Y, c->bps, st,
-                             block_product_splits(c->n, c->np, b, c->bpart_elems), c->bpart);
+                             block_product_splits(c->n, c->np, b, c->bpart_elems), c->bpart,
+                             0);    // the mean message ws in FP32 (BF16 modes)
     }
     // Z = Y - g^2 M (M^T Bs)
     HIP_TRY(hipMemcpyAsync(c->sm_Z, c->sm_Y, (size_t)c->n * c->bps * sizeof(float),

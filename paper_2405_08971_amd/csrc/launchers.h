@@ -93,10 +93,14 @@ void launch_finish_record(const LoopState* ls, const double* L, const double* Li
                           hipStream_t st);
 
 // ---- block_product.hip
+// fp32_col >= 0 (BF16 modes): that column is also summed in FP32 from the FP32 kernel
+// entries (chunk sums in FP64) and replaces the column's MFMA result; the FP32 mode sums
+// every column that way.
 void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
                           const float4* Xo, int m, int mp, const float* B, int ldb, int bcols,
                           __bf16* Bth, __bf16* Btl, float sigma_f2, float* out, int ldo,
-                          hipStream_t st, int nsplit = 1, float* part = nullptr);
+                          hipStream_t st, int nsplit = 1, float* part = nullptr,
+                          int fp32_col = -1);
 // number of observation-axis splits for a block product of n rows (see launch_block_product)
 int block_product_splits(int n, int mp, int bcols, size_t part_elems);
 
