@@ -69,6 +69,10 @@ def parse():
                         "transcendental peak of the roofline)")
     p.add_argument("--no-accuracy", action="store_true",
                    help="skip the FP64-reference and precision-replay comparisons")
+    p.add_argument("--fp64-horizon", type=int, default=0,
+                   help="instead of the benchmark: run both modes with their own CG actions "
+                        "for this many steps beside the FP64 oracle replaying each run's "
+                        "actions (minutes of host time), print the per-step errors")
     p.add_argument("--replay-steps", type=int, default=200,
                    help="steps of the BF16X3-vs-FP32 replay with shared CG actions")
     return p.parse_args()
@@ -488,6 +492,64 @@ def cpu_baseline(cfg, wl, kept):
     return base, err
 
 
+def fp64_horizon(cfg, X, wl, T):
+    """Each mode's own CG run (headline BF16X3 and FP32-plain) over T steps beside the FP64
+    oracle replaying that run's actions step by step (the batch update of Alg. 2, then the
+    truncation of Sec. 3.2): per step, the relative mean error of the mean and of the
+    marginal variance on the 2048-point subset, and the condition number of the step's
+    projected Gram matrix S^T Ghat S (from the run's FP64 Cholesky factor)."""
+    import torch
+    from oracle.cakf import Model, run_filter
+    from paper_2405_08971_amd.filter import Record
+    threads = max(1, min(16, os.cpu_count() or 1))
+    os.environ["ORACLE_THREADS"] = str(threads)
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(threads)
+    except Exception:
+        pass
+    model = Model(wl.X.astype(np.float32).astype(np.float64), cfg.nu2, cfg.ell, cfg.sigma_f2,
+                  cfg.a, cfg.noise_var, cfg.dist)
+    sub = wl.subset(2048)
+    rows = torch.from_numpy(sub.astype(np.int32)).cuda()
+    runs = {"bf16x3": make_filter(cfg, X, "bf16x3", policy="cg"),
+            "fp32": make_filter(cfg, X, "fp32", policy="cg")}
+    oracle_state = {p: (None, None) for p in runs}
+    per_step = {p: [] for p in runs}
+    t0 = time.perf_counter()
+    for k in range(1, T + 1):
+        idx, y = wl.step(k)
+        idx_d = torch.from_numpy(idx.astype(np.int32)).cuda()
+        y_d = torch.from_numpy(y.astype(np.float32)).cuda()
+        for prec, f in runs.items():
+            rec = Record(cfg.m, cfg.i)
+            f.step(idx_d, y_d, record=rec)
+            na = int(rec.n_actions.item())
+            S = rec.S.cpu().numpy()[:, :na].astype(np.float64)
+            L = rec.chol.cpu().numpy()[:na, :na]
+            mean = f.state()[0][rows.long()].cpu().numpy()
+            var = f.marginal_var(rows).cpu().numpy()
+            m0, M0 = oracle_state[prec]
+            r, = run_filter(model, [(idx.astype(np.int64), y.astype(np.float32).astype(np.float64))],
+                            cfg.i, cfg.r, policy="given", actions=[S], form="batch", m0=m0, M0=M0)
+            oracle_state[prec] = (r.m, r.M_plus)
+            sv = np.linalg.svd(L, compute_uv=False)
+            per_step[prec].append(dict(
+                step=k, mean=err_fields(mean, r.m[sub])[0],
+                var=err_fields(var, cfg.sigma_f2 - np.sum(r.M_plus[sub] ** 2, axis=1))[0],
+                cond=float((sv[0] / sv[-1]) ** 2)))
+        print(f"step {k}: " + ", ".join(f"{p} mean {v[-1]['mean']:.2e} var {v[-1]['var']:.2e}"
+                                        f" cond {v[-1]['cond']:.1e}"
+                                        for p, v in per_step.items())
+              + f" ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    for f in runs.values():
+        f.close()
+    out = {"workload": cfg.name, "steps": T, "subset": 2048, "per_step": per_step}
+    for prec, v in per_step.items():
+        out[prec] = {key: max(e[key] for e in v) for key in ("mean", "var")}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -507,6 +569,10 @@ def main():
     cfg = CONFIGS[args.config]
     wl = Workload(cfg, seed=args.seed)
     X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
+    if args.fp64_horizon > 0:
+        print(json.dumps({"fp64_horizon": fp64_horizon(cfg, X, wl, args.fp64_horizon)}),
+              flush=True)
+        return
     nsteps = args.warmup + args.steps + 3
     inputs = device_inputs(wl, range(1, nsteps + 1))
     torch.cuda.synchronize()

@@ -171,7 +171,9 @@ int cakf_state(cakf_ctx* ctx, float** mean, float** factor, int* ld, int* rank);
 int cakf_copy_state(cakf_ctx* ctx, float* mean, float* factor, int ld);
 
 /* Copy a state in (device buffers: mean N, factor N x rank with leading dimension ld).
- * rank <= max_rank. */
+ * rank <= max_rank + max_actions: a factor with more than max_rank columns is an
+ * untruncated one, which cakf_truncate reduces (cakf_update needs rank <= max_rank and
+ * returns CAKF_E_STATE otherwise). */
 int cakf_set_state(cakf_ctx* ctx, const float* mean, const float* factor, int ld, int rank);
 
 /* Predict (Alg. 1): m <- a m, M <- a M. */

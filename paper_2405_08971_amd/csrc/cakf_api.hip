@@ -567,7 +567,7 @@ extern "C" int cakf_copy_state(cakf_ctx* c, float* mean, float* factor, int ld) 
 
 extern "C" int cakf_set_state(cakf_ctx* c, const float* mean, const float* factor, int ld,
                               int rank) {
-    if (!c || !mean || rank < 0 || rank > c->r || (rank > 0 && (!factor || ld < rank)))
+    if (!c || !mean || rank < 0 || rank > c->Kmax || (rank > 0 && (!factor || ld < rank)))
         return CAKF_E_ARG;
     HIP_TRY(hipMemcpyAsync(c->mean, mean, (size_t)c->N * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
@@ -704,30 +704,26 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
         const int rc = block_rounds(c, d, imax, st);
         if (rc) return rc;
     } else if (d.rank > 0) {
-        if (cg) {
-            int nb = 0;
-            launch_colsum_partial(c->Mo, c->ldmo, m, d.rank, c->r0, 1, c->mpart, c->ldmo, st, &nb);
-            launch_colsum_final(c->mpart, c->ldmo, nb, d.rank, c->T, 1, st);
-        } else {
-            // T = Mo^T S, stored column-major (rank x imax, ld ldmo): T[l * ldmo + c]
-            const float one = 1.0f, zero = 0.0f;
-            BLAS_TRY(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose,
-                                   d.rank, c->imax, m, &one, c->Mo, c->ldmo, c->S, c->imax,
-                                   &zero, c->T, c->ldmo));
-        }
+        // t_0 = Mo^T s_0 (s_0 = r0 for CG, the first given action otherwise), column 0 of
+        // T (rank x imax, column-major, ld ldmo); the later columns are formed one per
+        // action, the partial sums in next_action and their FP64 sum in sym_tiles
+        int nb = 0;
+        launch_colsum_partial(c->Mo, c->ldmo, m, d.rank, cg ? c->r0 : c->S, cg ? 1 : c->imax,
+                              c->mpart, c->ldmo, st, &nb);
+        launch_colsum_final(c->mpart, c->ldmo, nb, d.rank, c->T, 1, st);
     }
     const int nu2 = c->cfg.kernel, dist = c->cfg.dist;
     const float noise = (float)c->cfg.noise_var;
     // column products of s_0
     int ncp = 0, nmpart = 0;
     if (!block)
-        launch_next_action(0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise, d, 0,
+        launch_next_action(0, 0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise, d, 0,
                            c->mpart, c->cpart, c->gs, c->ls, st, &ncp);
     for (int j = 0; j < (block ? 0 : imax); ++j) {
         {
             KernelTimer t(c, CAKF_PHASE_SYM_TILES);
             launch_sym_tiles(nu2, dist, c->cfg.prec != CAKF_PREC_FP32, c->Xo, c->S, d, j,
-                             c->part, (cg && j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart,
+                             c->part, (j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart,
                              c->T, c->cpart, ncp, c->gs, c->colvec, c->ls, st, t.start, t.stop);
         }
         int nfu = 0;
@@ -744,7 +740,7 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
         }
         if (j + 1 < imax) {
             PhaseTimer t(c, CAKF_PHASE_NEXT_ACTION);
-            launch_next_action(cg ? 1 : 0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise,
+            launch_next_action(cg ? 1 : 0, 1, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise,
                                d, j + 1, c->mpart, c->cpart, c->gs, c->ls, st, &ncp);
             nmpart = ncp;
         }
@@ -819,16 +815,36 @@ static int truncate_factor(cakf_ctx* c, const TruncWork& w, const float* M, int 
     bool picked = false;
     {
         PhaseTimer t(c, CAKF_PHASE_EIG);
-        // G = Q T Q^T in one cooperative launch, T's eigenvectors by divide and conquer,
-        // then only the r leading ones back-transformed (into V_r directly).  Larger K, or
-        // a device that cannot co-schedule the launch, takes the library's dense solver.
-        if (w.tdV && K >= 3 && K <= TD_MAXK) {
+        // G = Q T Q^T in one cooperative launch, the r leading eigenpairs of T (bisection,
+        // twisted factorisation, clusters by inverse iteration), back-transformed into V_r
+        // directly.  Larger K, or a device that cannot co-schedule the launch, takes the
+        // library's dense solver.
+        // work area of the Gram's partial sums (consumed by now): Z, Z X, E, E^2, lam
+        const size_t need = 2 * (size_t)K * r + 2 * (size_t)r * r + tri_eigen_work_elems(K, r);
+        if (w.tdV && K >= 3 && K <= TD_MAXK && K <= tri_eigen_max_k() && need <= w.gwork_elems) {
             if (launch_tridiag(w.G, K, w.tdV, w.tdtau, w.eigval, w.offdiag, w.tdp, w.tdrow,
                                w.tdctr, w.tdabort, st) == hipSuccess) {
                 hipLaunchKernelGGL(k_note_abort, dim3(1), dim3(1), 0, st, w.tdabort, c->diag);
-                BLAS_TRY(rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, K, w.eigval,
-                                          w.offdiag, w.G, K, w.info));
-                launch_backtransform(w.G, w.tdV, w.tdtau, K, r, w.Vr, rotation, st);
+                double* Zr = w.gwork;                       // K x r row-major = Z^T col-major
+                double* Zx = Zr + (size_t)K * r;
+                double* E = Zx + (size_t)K * r;
+                double* E2 = E + (size_t)r * r;
+                launch_tri_eigen(w.eigval, w.offdiag, K, r, E2 + (size_t)r * r, Zr, st);
+                // symmetric orthogonalisation Z X, X = I - E/2 + 3/8 E^2, E = Z^T Z - I: the
+                // twisted vectors of closely spaced eigenvalues are orthogonal only to about
+                // eps ||T|| / gap; mixing within the kept subspace leaves M V_r V_r^T M^T as
+                // it is.  Column-major: Zt = Z^T (r x K, ld r), E = Zt Zt^T, Zt X = (Z X)^T.
+                const double one = 1.0, zero = 0.0;
+                BLAS_TRY(rocblas_dgemm(c->blas, rocblas_operation_none,
+                                       rocblas_operation_transpose, r, r, K, &one, Zr, r, Zr,
+                                       r, &zero, E, r));
+                launch_lowdin(E, E2, r, 0, st);
+                BLAS_TRY(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none,
+                                       r, r, r, &one, E, r, E, r, &zero, E2, r));
+                launch_lowdin(E, E2, r, 1, st);
+                BLAS_TRY(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none,
+                                       r, K, r, &one, E2, r, Zr, r, &zero, Zx, r));
+                launch_backtransform(Zx, r, 1, w.tdV, w.tdtau, K, r, w.Vr, rotation, st);
                 picked = true;
             } else {
                 (void)hipGetLastError();

@@ -222,6 +222,426 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
                                       0, st);
 }
 
+// ------------------------------------------------------ tridiagonal eigenproblem (top r)
+// The r largest eigenpairs of the symmetric tridiagonal T (diagonal d, off-diagonal e),
+// computed independently of one another:
+//   eigenvalues  by bisection on Sturm counts (the number of negative pivots of the
+//                LDL^T factorisation of T - sigma I is the number of eigenvalues below
+//                sigma), one wave per eigenvalue; each lane follows four shifts at once,
+//                so a round tests 256 shifts and shrinks the bracket 257-fold;
+//   eigenvectors by the twisted factorisation of T - lambda I: the forward factor
+//                L D L^T and the backward factor U D' U^T meet at the index k where the
+//                twist element gamma_k = D_k + D'_k - (d_k - lambda) is smallest in
+//                magnitude, and z is obtained from z_k = 1 outwards with the two factors'
+//                multipliers (two lanes per eigenvector, the pivots kept in LDS);
+//   ties         eigenvalues within TRI_CTOL ||T|| of a neighbour (repeated eigenvalues)
+//                are recomputed by inverse iteration from distinct starting vectors, each
+//                iterate orthogonalised against the tie's earlier vectors (one wave per
+//                tie), since their twisted vectors can coincide.
+// Vectors of distinct eigenvalues that lie close together (absolute gaps far below ||T||,
+// as in the graded spectra of a truncation Gram matrix) carry errors of order
+// eps ||T|| / gap and are left slightly non-orthogonal; the caller restores orthogonality
+// with the symmetric correction Z (Z^T Z)^{-1/2} (launch_lowdin_x).
+// Output: Zr (row-major K x r, column c the eigenvector of the c-th largest eigenvalue).
+constexpr double TRI_CTOL = 1e-13;
+constexpr int TRI_ITERS = 3;
+constexpr int TRI_MAXK = 1280;         // LDS of the cluster kernel (6 K doubles)
+constexpr int TW_VPB = 8;              // eigenvectors per workgroup of the twisted kernel
+constexpr int TW_MAXK = 640;           // LDS of the twisted kernel (3 TW_VPB K doubles)
+
+// Gershgorin bounds of T widened by rounding, ||T|| and the pivot floor, per workgroup.
+__device__ void tri_bounds(const double* __restrict__ d, const double* __restrict__ e, int K,
+                           double* red, double& glo, double& ghi, double& tnorm,
+                           double& pivmin) {
+    double lo = 1e300, hi = -1e300, emax = 0.0;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+        const double a = i > 0 ? fabs(e[i - 1]) : 0.0, b = i + 1 < K ? fabs(e[i]) : 0.0;
+        lo = fmin(lo, d[i] - a - b);
+        hi = fmax(hi, d[i] + a + b);
+        emax = fmax(emax, b * b);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int off = 32; off >= 1; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+        emax = fmax(emax, __shfl_xor(emax, off, 64));
+    }
+    if (lane == 0) {
+        red[3 * w] = lo;
+        red[3 * w + 1] = hi;
+        red[3 * w + 2] = emax;
+    }
+    __syncthreads();
+    lo = red[0];
+    hi = red[1];
+    emax = red[2];
+    for (int k = 1; k < nw; ++k) {
+        lo = fmin(lo, red[3 * k]);
+        hi = fmax(hi, red[3 * k + 1]);
+        emax = fmax(emax, red[3 * k + 2]);
+    }
+    __syncthreads();
+    tnorm = fmax(fabs(lo), fabs(hi));
+    pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
+    const double pad = 2.0 * 2.220446049250313e-16 * tnorm + 2.0 * pivmin;
+    glo = lo - pad;
+    ghi = hi + pad;
+}
+
+// 1 / q by the hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double tri_rcp(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = __builtin_fma(__builtin_fma(-q, r, 1.0), r, r);
+    return __builtin_fma(__builtin_fma(-q, r, 1.0), r, r);
+}
+
+// One Sturm step: the next pivot, floored at -pivmin when it is too small.
+__device__ __forceinline__ double tri_pivot(double dmin, double e2, double q, double pivmin) {
+    const double v = __builtin_fma(-e2, tri_rcp(q), dmin);
+    return fabs(v) < pivmin ? -pivmin : v;
+}
+
+// lam[c] (c < r) = the c-th largest eigenvalue; info[0..1] = ||T||, pivot floor.
+__global__ __launch_bounds__(256) void k_tri_bisect(const double* __restrict__ d,
+                                                    const double* __restrict__ e, int K, int r,
+                                                    double* __restrict__ lam,
+                                                    double* __restrict__ info) {
+    __shared__ double dl[TRI_MAXK], e2[TRI_MAXK];
+    __shared__ double red[12];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+        dl[i] = d[i];
+        e2[i] = i + 1 < K ? e[i] * e[i] : 0.0;
+    }
+    double glo, ghi, tnorm, pivmin;
+    tri_bounds(d, e, K, red, glo, ghi, tnorm, pivmin);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        info[0] = tnorm;
+        info[1] = pivmin;
+    }
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= r) return;
+    const int t = K - 1 - c;                 // ascending index of the eigenvalue
+    double lo = glo, hi = ghi;
+    // to an absolute accuracy of about eps ||T|| (the accuracy to which the Householder
+    // reduction determines the eigenvalues of the Gram matrix)
+    const double abstol = 2.220446049250313e-16 * tnorm + pivmin;
+    for (int round = 0; round < 12; ++round) {
+        if (hi - lo <= 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + abstol) break;
+        // shifts g = 4 lane + s, s = 0..3, at lo + (hi - lo) (g + 1) / 257
+        const double h = (hi - lo) / 257.0;
+        double sg[4], q[4];
+        int cnt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sg[u] = lo + h * (double)(4 * lane + u + 1);
+            q[u] = dl[0] - sg[u];
+            if (fabs(q[u]) < pivmin) q[u] = -pivmin;
+            cnt[u] = q[u] < 0.0;
+        }
+        for (int i = 1; i < K; ++i) {
+            const double di = dl[i], ei = e2[i - 1];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                q[u] = tri_pivot(di - sg[u], ei, q[u], pivmin);
+                cnt[u] += q[u] < 0.0;
+            }
+        }
+        // the first shift with more than t eigenvalues below it
+        int first = 4;
+#pragma unroll
+        for (int u = 3; u >= 0; --u)
+            if (cnt[u] >= t + 1) first = u;
+        const unsigned long long above = __ballot(first < 4);
+        const int l = above ? __builtin_ctzll(above) : 64;
+        const int fl = l < 64 ? __shfl(first, l, 64) : 4;
+        const int g = l < 64 ? 4 * l + fl : 256;          // 0..256
+        const double nlo = g == 0 ? lo : lo + h * (double)g;
+        const double nhi = g == 256 ? hi : lo + h * (double)(g + 1);
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0) lam[c] = 0.5 * (lo + hi);
+}
+
+// Twisted-factorisation eigenvectors, TW_VPB per workgroup of one wave: lane 2v runs the
+// forward factorisation of eigenvector v and lane 2v + 1 the backward one, the pivots
+// kept in LDS; the twist index is chosen by the whole wave, then the same two lanes
+// extend z below and above it, and the wave normalises.
+__global__ __launch_bounds__(64) void k_tri_twisted(const double* __restrict__ d,
+                                                    const double* __restrict__ e, int K, int r,
+                                                    const double* __restrict__ lam,
+                                                    const double* __restrict__ info,
+                                                    double* __restrict__ Zr) {
+    __shared__ double dl[TW_MAXK], el[TW_MAXK];
+    __shared__ double Dv[TW_VPB][TW_MAXK], Dpv[TW_VPB][TW_MAXK], zv[TW_VPB][TW_MAXK];
+    __shared__ int kb_s[TW_VPB];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < K; i += 64) {
+        dl[i] = d[i];
+        el[i] = i + 1 < K ? e[i] : 0.0;
+    }
+    __syncthreads();
+    const double pivmin = info[1];
+    const int v = lane >> 1, side = lane & 1;
+    const int c = blockIdx.x * TW_VPB + v;
+    const bool act = v < TW_VPB && c < r;
+    const double lm = act ? lam[c] : 0.0;
+    if (act) {
+        if (side == 0) {
+            // forward: T - lm I = L D L^T,  D_{i+1} = (d_{i+1} - lm) - e_i^2 / D_i
+            double Dc = dl[0] - lm;
+            for (int i = 0; i + 1 < K; ++i) {
+                if (fabs(Dc) < pivmin) Dc = pivmin;
+                Dv[v][i] = Dc;
+                Dc = __builtin_fma(-el[i] * el[i], tri_rcp(Dc), dl[i + 1] - lm);
+            }
+            Dv[v][K - 1] = Dc;
+        } else {
+            // backward: T - lm I = U D' U^T,  D'_{i-1} = (d_{i-1} - lm) - e_{i-1}^2 / D'_i
+            double Dc = dl[K - 1] - lm;
+            for (int i = K - 1; i >= 1; --i) {
+                if (fabs(Dc) < pivmin) Dc = pivmin;
+                Dpv[v][i] = Dc;
+                Dc = __builtin_fma(-el[i - 1] * el[i - 1], tri_rcp(Dc), dl[i - 1] - lm);
+            }
+            Dpv[v][0] = Dc;
+        }
+    }
+    __syncthreads();
+    // twist index of each vector: smallest |gamma_k|, ties to the lowest k (wave argmin)
+    for (int vv = 0; vv < TW_VPB; ++vv) {
+        const int cc = blockIdx.x * TW_VPB + vv;
+        if (cc >= r) break;
+        const double lv = lam[cc];
+        double best = 1e308;
+        int kbest = K;
+        for (int k = lane; k < K; k += 64) {
+            const double g = fabs(Dv[vv][k] + Dpv[vv][k] - (dl[k] - lv));
+            if (g < best) {
+                best = g;
+                kbest = k;
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int ok = __shfl_xor(kbest, off, 64);
+            if (ob < best || (ob == best && ok < kbest)) {
+                best = ob;
+                kbest = ok;
+            }
+        }
+        if (lane == 0) kb_s[vv] = kbest;
+    }
+    __syncthreads();
+    if (act) {
+        const int kb = kb_s[v];
+        if (side == 0) {
+            // below the twist: z_i = -(e_i / D_i) z_{i+1}
+            double z = 1.0;
+            zv[v][kb] = 1.0;
+            for (int i = kb - 1; i >= 0; --i) {
+                z = -el[i] * tri_rcp(Dv[v][i]) * z;
+                zv[v][i] = z;
+            }
+        } else {
+            // above the twist: z_i = -(e_{i-1} / D'_i) z_{i-1}
+            double z = 1.0;
+            for (int i = kb + 1; i < K; ++i) {
+                z = -el[i - 1] * tri_rcp(Dpv[v][i]) * z;
+                zv[v][i] = z;
+            }
+        }
+    }
+    __syncthreads();
+    for (int vv = 0; vv < TW_VPB; ++vv) {
+        const int cc = blockIdx.x * TW_VPB + vv;
+        if (cc >= r) break;
+        double nn = 0.0;
+        for (int k = lane; k < K; k += 64) nn = __builtin_fma(zv[vv][k], zv[vv][k], nn);
+        nn = wave_sum(nn);
+        const double sc = 1.0 / sqrt(nn);
+        for (int k = lane; k < K; k += 64) Zr[(size_t)k * r + cc] = zv[vv][k] * sc;
+    }
+}
+
+// A reproducible starting vector entry in (-1, 1) for inverse iteration.
+__device__ __forceinline__ double tri_start(int i, int t) {
+    unsigned long long x = (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull ^
+                           (unsigned long long)(t + 1) * 0xD1B54A32D192ED03ull;
+    x ^= x >> 31;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 29;
+    return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Clusters among the top r: consecutive eigenvalues with lam[c] - lam[c+1] <= TRI_CTOL ||T||.
+// One wave per cluster (workgroups take clusters blockIdx.x, + gridDim.x, ...): for each
+// member t, the tridiagonal LU factorisation of T - lam_t I with partial pivoting (in LDS),
+// TRI_ITERS solves from a distinct starting vector, each result orthogonalised against the
+// cluster's earlier members and normalised; the member's column of Zr is replaced.
+__global__ __launch_bounds__(64) void k_tri_clusters(const double* __restrict__ d,
+                                                     const double* __restrict__ e, int K, int r,
+                                                     const double* __restrict__ lam,
+                                                     const double* __restrict__ info,
+                                                     double* __restrict__ Zr) {
+    __shared__ double fd[TRI_MAXK], fs1[TRI_MAXK], fs2[TRI_MAXK], fm[TRI_MAXK], x[TRI_MAXK];
+    __shared__ unsigned char pv[TRI_MAXK];
+    __shared__ int cl_start, cl_end;
+    const int lane = threadIdx.x;
+    const double tnorm = info[0];
+    const double ctol = TRI_CTOL * tnorm;
+    const double pert = 2.220446049250313e-16 * fmax(tnorm, 1e-300);
+    // no tie at all (the usual case): every lane checks its gaps, the wave leaves
+    {
+        bool tie = false;
+        for (int c = lane; c + 1 < r; c += 64) tie |= lam[c] - lam[c + 1] <= ctol;
+        if (!__ballot(tie)) return;
+    }
+    // the cluster this workgroup takes: count cluster starts in order (lane 0, r steps)
+    for (int want = blockIdx.x;; want += gridDim.x) {
+        if (lane == 0) {
+            int found = -1, cs = 0, ce = 0, idx = 0;
+            int c = 0;
+            while (c < r) {
+                int c1 = c;
+                while (c1 + 1 < r && lam[c1] - lam[c1 + 1] <= ctol) ++c1;
+                if (c1 > c) {
+                    if (idx == want) {
+                        found = 1;
+                        cs = c;
+                        ce = c1;
+                        break;
+                    }
+                    ++idx;
+                }
+                c = c1 + 1;
+            }
+            cl_start = found > 0 ? cs : -1;
+            cl_end = ce;
+        }
+        __syncthreads();
+        const int cs = cl_start, ce = cl_end;
+        __syncthreads();
+        if (cs < 0) return;
+        for (int t = cs; t <= ce; ++t) {
+            const double lm = lam[t];
+            // LU with partial pivoting of T - lm I: row i after elimination holds
+            // fd[i] (diagonal), fs1[i], fs2[i] (superdiagonals); fm[i] the multiplier of
+            // step i, pv[i] whether rows i, i+1 were swapped
+            if (lane == 0) {
+                double dg = d[0] - lm, s1 = K > 1 ? e[0] : 0.0, s2 = 0.0;
+                for (int i = 0; i + 1 < K; ++i) {
+                    const double sub = e[i];
+                    const double nd = d[i + 1] - lm, ns1 = i + 2 < K ? e[i + 1] : 0.0;
+                    if (fabs(sub) > fabs(dg)) {
+                        // swap rows i and i + 1
+                        const double m = dg / sub;
+                        fd[i] = sub;
+                        fs1[i] = nd;
+                        fs2[i] = ns1;
+                        fm[i] = m;
+                        pv[i] = 1;
+                        dg = s1 - m * nd;
+                        s1 = s2 - m * ns1;
+                        s2 = 0.0;
+                    } else {
+                        if (dg == 0.0) dg = pert;
+                        const double m = sub / dg;
+                        fd[i] = dg;
+                        fs1[i] = s1;
+                        fs2[i] = s2;
+                        fm[i] = m;
+                        pv[i] = 0;
+                        dg = nd - m * s1;
+                        s1 = ns1 - m * s2;
+                        s2 = 0.0;
+                    }
+                }
+                fd[K - 1] = dg == 0.0 ? pert : dg;
+                fs1[K - 1] = 0.0;
+                fs2[K - 1] = 0.0;
+            }
+            for (int i = lane; i < K; i += 64) x[i] = tri_start(i, t);
+            __syncthreads();
+            for (int it = 0; it < TRI_ITERS; ++it) {
+                if (lane == 0) {
+                    // forward elimination of the right-hand side, then back substitution
+                    for (int i = 0; i + 1 < K; ++i) {
+                        double a = x[i], b = x[i + 1];
+                        if (pv[i]) {
+                            const double tmp = a;
+                            a = b;
+                            b = tmp;
+                        }
+                        x[i] = a;
+                        x[i + 1] = b - fm[i] * a;
+                    }
+                    for (int i = K - 1; i >= 0; --i) {
+                        double s = x[i];
+                        if (i + 1 < K) s -= fs1[i] * x[i + 1];
+                        if (i + 2 < K) s -= fs2[i] * x[i + 2];
+                        const double dv = fabs(fd[i]) > pert ? fd[i] : (fd[i] >= 0.0 ? pert : -pert);
+                        x[i] = s / dv;
+                    }
+                }
+                __syncthreads();
+                // orthogonalise against the cluster's earlier members, then normalise
+                for (int s = cs; s < t; ++s) {
+                    double dot = 0.0;
+                    for (int i = lane; i < K; i += 64) dot = __builtin_fma(Zr[(size_t)i * r + s], x[i], dot);
+                    dot = wave_sum(dot);
+                    for (int i = lane; i < K; i += 64) x[i] = __builtin_fma(-dot, Zr[(size_t)i * r + s], x[i]);
+                    __syncthreads();
+                }
+                double nn = 0.0;
+                for (int i = lane; i < K; i += 64) nn = __builtin_fma(x[i], x[i], nn);
+                nn = wave_sum(nn);
+                const double sc = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+                for (int i = lane; i < K; i += 64) x[i] *= sc;
+                __syncthreads();
+            }
+            for (int i = lane; i < K; i += 64) Zr[(size_t)i * r + t] = x[i];
+            __syncthreads();
+        }
+    }
+}
+
+int tri_eigen_work_elems(int K, int r) { return r + 2; }
+int tri_eigen_max_k() { return TW_MAXK; }
+
+void launch_tri_eigen(const double* d, const double* e, int K, int r, double* work, double* Zr,
+                      hipStream_t st) {
+    double* lam = work;
+    double* info = work + r;
+    hipLaunchKernelGGL(k_tri_bisect, dim3((r + 3) / 4), dim3(256), 0, st, d, e, K, r, lam, info);
+    hipLaunchKernelGGL(k_tri_twisted, dim3((r + TW_VPB - 1) / TW_VPB), dim3(64), 0, st, d, e, K,
+                       r, lam, info, Zr);
+    hipLaunchKernelGGL(k_tri_clusters, dim3(32), dim3(64), 0, st, d, e, K, r, lam, info, Zr);
+}
+
+// X = I - E/2 + (3/8) E2 for the symmetric correction Z X ~ Z (Z^T Z)^{-1/2}, given
+// E = Z^T Z - I (E holds Z^T Z on entry and is turned into E in place, E2 = E E is formed
+// by the caller in between: mode 0 subtracts I, mode 1 forms X into E2).
+__global__ void k_lowdin(double* __restrict__ E, double* __restrict__ E2, int r, int mode) {
+    const size_t total = (size_t)r * r;
+    for (size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const bool diag = x / r == x % r;
+        if (mode == 0) {
+            if (diag) E[x] -= 1.0;
+        } else {
+            E2[x] = (diag ? 1.0 : 0.0) - 0.5 * E[x] + 0.375 * E2[x];
+        }
+    }
+}
+
+void launch_lowdin(double* E, double* E2, int r, int mode, hipStream_t st) {
+    const size_t total = (size_t)r * r;
+    hipLaunchKernelGGL(k_lowdin, dim3((int)std::min<size_t>((total + 255) / 256, 2048)), dim3(256),
+                       0, st, E, E2, r, mode);
+}
+
 // ------------------------------------------------------------------ back-transformation
 // V_r = Q Z_r for the r leading eigenvectors of T: Z holds T's eigenvectors as columns
 // (column-major, ascending eigenvalues), so output column c (descending order) starts as
@@ -234,6 +654,7 @@ constexpr int BT_CHUNK = 8;
 
 template <int U>
 __global__ __launch_bounds__(256) void k_backtransform(const double* __restrict__ Z,
+                                                       long long zrs, long long zcs,
                                                        const double* __restrict__ Vh,
                                                        const double* __restrict__ tau, int K,
                                                        int r, float* __restrict__ Vr,
@@ -248,7 +669,7 @@ __global__ __launch_bounds__(256) void k_backtransform(const double* __restrict_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int k = lane + 64 * u;
-        z[u] = (col < r && k < K) ? Z[(size_t)(K - 1 - col) * K + k] : 0.0;
+        z[u] = (col < r && k < K) ? Z[(long long)k * zrs + (long long)col * zcs] : 0.0;
     }
     // the chunk of reflectors j0, j0 - 1, .. (v_j[j + 1] = 1, zero above) into registers
     double pv[PER], pt = 0.0;
@@ -300,13 +721,14 @@ __global__ __launch_bounds__(256) void k_backtransform(const double* __restrict_
     }
 }
 
-void launch_backtransform(const double* Z, const double* Vh, const double* tau, int K, int r,
-                          float* Vr, double* rot, hipStream_t st) {
+void launch_backtransform(const double* Z, long long zrs, long long zcs, const double* Vh,
+                          const double* tau, int K, int r, float* Vr, double* rot,
+                          hipStream_t st) {
     const int blocks = (r + 3) / 4;
     const int u = (K + 63) / 64;
 #define CAKF_BT(N)                                                                          \
-    hipLaunchKernelGGL(k_backtransform<N>, dim3(blocks), dim3(256), 0, st, Z, Vh, tau, K, r, \
-                       Vr, rot)
+    hipLaunchKernelGGL(k_backtransform<N>, dim3(blocks), dim3(256), 0, st, Z, zrs, zcs, Vh,  \
+                       tau, K, r, Vr, rot)
     if (u <= 2) CAKF_BT(2);
     else if (u <= 4) CAKF_BT(4);
     else if (u <= 6) CAKF_BT(6);

@@ -81,10 +81,14 @@ void launch_round_gram(const float* U, const float* V, const float* S, const flo
                        hipStream_t st);
 void launch_round_mot(const float* Mo, const float* S, const ObsDims& d, int j0, int bt,
                       float* part, float* T, hipStream_t st);
-void launch_next_action(int resid, const float* U, const float* Mo, const float* r0, float* S,
-                        float* V, const double* beta, const float* T, float noise_var,
-                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
-                        const LoopState* ls, hipStream_t st, int* nblk_out);
+// resid: the CG residual is the action (else the action is read from S); mopart: also form
+// the per-block partial sums of Mo^T s_jt (always with resid), finished by the next
+// sym_tiles launch into column jt of T
+void launch_next_action(int resid, int mopart, const float* U, const float* Mo,
+                        const float* r0, float* S, float* V, const double* beta,
+                        const float* T, float noise_var, const ObsDims& d, int jt,
+                        float* mpart, double* cpart, int gs, const LoopState* ls,
+                        hipStream_t st, int* nblk_out);
 void launch_build_block(const float* S, const double* LinvT, const double* beta,
                         const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
                         float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st);
@@ -150,8 +154,21 @@ int tridiag_workgroups(int K);
 hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double* d, double* e,
                           double* pbuf, double* rowbuf, unsigned* ctr, int* abort_flag,
                           hipStream_t st);
-void launch_backtransform(const double* Z, const double* Vh, const double* tau, int K, int r,
-                          float* Vr, double* rot, hipStream_t st);
+// V_r = Q Z_r: element (k, c) of Z_r (the eigenvector of the c-th largest eigenvalue of the
+// tridiagonal) at Z[k * zrs + c * zcs]
+void launch_backtransform(const double* Z, long long zrs, long long zcs, const double* Vh,
+                          const double* tau, int K, int r, float* Vr, double* rot,
+                          hipStream_t st);
+// the r largest eigenpairs of the symmetric tridiagonal (d, e) of order
+// K <= tri_eigen_max_k(): Zr (row-major K x r, descending eigenvalues), orthogonal up to
+// eps ||T|| / (absolute eigenvalue gap); work: tri_eigen_work_elems(K, r) doubles
+int tri_eigen_work_elems(int K, int r);
+int tri_eigen_max_k();
+void launch_tri_eigen(const double* d, const double* e, int K, int r, double* work, double* Zr,
+                      hipStream_t st);
+// steps of the symmetric orthogonalisation Z X, X = I - E/2 + (3/8) E^2, E = Z^T Z - I
+// (r x r, FP64): mode 0 turns Z^T Z into E in place, mode 1 writes X over E2 = E E
+void launch_lowdin(double* E, double* E2, int r, int mode, hipStream_t st);
 
 // ---- probe.hip
 // lane operations per second of v_exp_f32, v_sqrt_f32 and v_fma_f32 (out: 3 doubles)

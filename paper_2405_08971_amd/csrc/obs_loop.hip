@@ -538,23 +538,26 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
                                                      const double* __restrict__ beta,
                                                      const float* __restrict__ T,
                                                      float noise_var, ObsDims d, int jt,
+                                                     int mopart,
                                                      float* __restrict__ mpart,
                                                      double* __restrict__ cpart, int gs,
                                                      const LoopState* __restrict__ ls) {
     if (ls->stop) return;
-    __shared__ float mred[RESID ? 4 : 1][RESID ? 64 * CPL : 1];
+    __shared__ float mred[4][64 * CPL];
     __shared__ double gred[4][64 * LPL], qred[4][64 * LPL];
     __shared__ double sred[2][4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int p0 = (blockIdx.x * 4 + w) * RW;
     const int j = jt - 1;
-    const bool lowrank = RESID && d.rank > 0;
+    // lowrank: this pass also forms the partial sums of Mo^T s_jt (mopart; the CG residual
+    // needs Mo t_j as well)
+    const bool lowrank = (RESID || mopart) && d.rank > 0;
     float tj[CPL], acc[CPL], bl[LPL];
     double g[LPL], q[LPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int c = lane * CPL + k;
-        tj[k] = (lowrank && c < d.rank) ? T[(size_t)j * d.ldmo + c] : 0.0f;
+        tj[k] = (RESID && lowrank && c < d.rank) ? T[(size_t)j * d.ldmo + c] : 0.0f;
         acc[k] = 0.0f;
     }
 #pragma unroll
@@ -639,7 +642,7 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
     // block sums over the 4 waves, fixed order
     if (lowrank) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) mred[RESID ? w : 0][RESID ? lane * CPL + k : 0] = acc[k];
+        for (int k = 0; k < CPL; ++k) mred[w][lane * CPL + k] = acc[k];
     }
 #pragma unroll
     for (int v = 0; v < LPL; ++v) {
@@ -653,8 +656,7 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
     __syncthreads();
     if (lowrank) {
         for (int c = threadIdx.x; c < d.rank; c += 256)
-            mpart[(size_t)blockIdx.x * d.ldmo + c] =
-                (mred[0][c] + mred[RESID ? 1 : 0][c]) + (mred[RESID ? 2 : 0][c] + mred[RESID ? 3 : 0][c]);
+            mpart[(size_t)blockIdx.x * d.ldmo + c] = (mred[0][c] + mred[1][c]) + (mred[2][c] + mred[3][c]);
     }
     double* out = cpart + (size_t)blockIdx.x * gs;
     for (int pos = threadIdx.x; pos < 2 * jt + 2; pos += 256) {
@@ -675,49 +677,63 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
 template <bool RESID, int CPL, int LPL>
 static void launch_na(int blocks, const float* U, const float* Mo, const float* r0, float* S,
                       float* V, const double* beta, const float* T, float noise_var,
-                      const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
-                      const LoopState* ls, hipStream_t st) {
+                      const ObsDims& d, int jt, int mopart, float* mpart, double* cpart,
+                      int gs, const LoopState* ls, hipStream_t st) {
     constexpr int RW = next_action_rows_per_wave(CPL, LPL);
     hipLaunchKernelGGL((k_next_action<RESID, CPL, LPL, RW>), dim3(blocks), dim3(256), 0, st, U,
-                       Mo, r0, S, V, beta, T, noise_var, d, jt, mpart, cpart, gs, ls);
+                       Mo, r0, S, V, beta, T, noise_var, d, jt, mopart, mpart, cpart, gs, ls);
 }
 
 template <bool RESID, int CPL>
 static void launch_na_l(int lpl, int blocks, const float* U, const float* Mo, const float* r0,
                         float* S, float* V, const double* beta, const float* T, float noise_var,
-                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
-                        const LoopState* ls, hipStream_t st) {
+                        const ObsDims& d, int jt, int mopart, float* mpart, double* cpart,
+                        int gs, const LoopState* ls, hipStream_t st) {
     if (lpl == 1)
-        launch_na<RESID, CPL, 1>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
-                                 cpart, gs, ls, st);
+        launch_na<RESID, CPL, 1>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
+                                 mpart, cpart, gs, ls, st);
     else if (lpl == 2)
-        launch_na<RESID, CPL, 2>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
-                                 cpart, gs, ls, st);
+        launch_na<RESID, CPL, 2>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
+                                 mpart, cpart, gs, ls, st);
     else
-        launch_na<RESID, CPL, 4>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
-                                 cpart, gs, ls, st);
+        launch_na<RESID, CPL, 4>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
+                                 mpart, cpart, gs, ls, st);
 }
 
-void launch_next_action(int resid, const float* U, const float* Mo, const float* r0, float* S,
-                        float* V, const double* beta, const float* T, float noise_var,
-                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
-                        const LoopState* ls, hipStream_t st, int* nblk_out) {
+template <bool RESID>
+static void launch_na_c(int cpl, int lpl, int blocks, const float* U, const float* Mo,
+                        const float* r0, float* S, float* V, const double* beta,
+                        const float* T, float noise_var, const ObsDims& d, int jt, int mopart,
+                        float* mpart, double* cpart, int gs, const LoopState* ls,
+                        hipStream_t st) {
+    if (cpl == 4)
+        launch_na_l<RESID, 4>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
+                              mpart, cpart, gs, ls, st);
+    else if (cpl == 8)
+        launch_na_l<RESID, 8>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
+                              mpart, cpart, gs, ls, st);
+    else
+        launch_na_l<RESID, 16>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
+                               mpart, cpart, gs, ls, st);
+}
+
+void launch_next_action(int resid, int mopart, const float* U, const float* Mo,
+                        const float* r0, float* S, float* V, const double* beta,
+                        const float* T, float noise_var, const ObsDims& d, int jt,
+                        float* mpart, double* cpart, int gs, const LoopState* ls,
+                        hipStream_t st, int* nblk_out) {
+    // the lanes cover the factor columns whenever Mo is read (CG residual or mopart)
+    const bool reads_mo = (resid || mopart) && d.rank > 0;
     const int lpl = next_action_lpl(d.imax);
-    const int cpl = resid ? next_action_cpl(d.ldmo) : 4;
+    const int cpl = reads_mo ? next_action_cpl(d.ldmo) : 4;
     const int blocks = next_action_blocks(d.m, cpl, lpl);
     *nblk_out = blocks;
-    if (!resid)
-        launch_na_l<false, 4>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
-                              cpart, gs, ls, st);
-    else if (cpl == 4)
-        launch_na_l<true, 4>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
-                             cpart, gs, ls, st);
-    else if (cpl == 8)
-        launch_na_l<true, 8>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
-                             cpart, gs, ls, st);
+    if (resid)
+        launch_na_c<true>(cpl, lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, 1,
+                          mpart, cpart, gs, ls, st);
     else
-        launch_na_l<true, 16>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mpart,
-                              cpart, gs, ls, st);
+        launch_na_c<false>(cpl, lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt,
+                           mopart ? 1 : 0, mpart, cpart, gs, ls, st);
 }
 
 // ------------------------------------------------------------------ block-residual policy

@@ -1,0 +1,62 @@
+"""The truncation's eigensolver (Sec. 3.2: the leading r eigenvectors of M^T M) on crafted
+factors whose Gram matrices have clustered and repeated eigenvalues, the cases where
+eigenvectors computed one at a time need not come out orthogonal.  Checked through the
+rotation V_r that cakf_truncate returns, against the definition: orthonormal columns,
+M^T M V_r = V_r diag(lambda) with lambda the r largest eigenvalues of M^T M (FP64 Gram of
+the device factor, host eigenvalues), and the truncated factor equal to M V_r."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _spectrum(kind, K, r):
+    s = np.logspace(1, -3, K)                  # singular values, distinct
+    if kind == "near_pairs":                   # pairs 1e-9 apart (relative)
+        s[1::2] = s[0::2][: len(s[1::2])] * (1 - 1e-9)
+    elif kind == "tie_across_cutoff":          # 12 equal values around position r
+        s[r - 6:r + 6] = s[r - 6]
+    elif kind == "all_equal":
+        s[:] = 1.0
+    elif kind == "two_blocks":                 # two blocks of equal values inside the top r
+        s[3:13] = s[3]
+        s[20:28] = s[20]
+    return np.sort(s)[::-1]
+
+
+@pytest.mark.parametrize("kind", ["distinct", "near_pairs", "tie_across_cutoff", "two_blocks",
+                                  "all_equal"])
+@pytest.mark.parametrize("K,r", [(64, 48), (190, 170)])
+def test_truncation_eigenvectors(kind, K, r):
+    import torch
+    from paper_2405_08971_amd.filter import CAKF
+
+    n = 1500
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((n, 3))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    f = CAKF(torch.from_numpy(X.astype(np.float32)).cuda(), nu2=3, lengthscale=0.3,
+             noise_var=0.05, ou_coeff=0.8, max_obs=16, max_actions=K - r, max_rank=r,
+             policy="given")
+    U, _ = np.linalg.qr(rng.standard_normal((n, K)))
+    Vt, _ = np.linalg.qr(rng.standard_normal((K, K)))
+    M = ((U * _spectrum(kind, K, r)) @ Vt).astype(np.float32)
+    Md = torch.from_numpy(M).cuda()
+    f.set_state(torch.zeros(n, device="cuda"), Md)
+    rot = torch.zeros((K, r), dtype=torch.float64, device="cuda")
+    f.truncate(rot)
+    Mp = f.state()[1]
+    torch.cuda.synchronize()
+    G = (Md.double().T @ Md.double()).cpu().numpy()
+    lam_ref = np.sort(np.linalg.eigvalsh(G))[::-1][:r]
+    V = rot.cpu().numpy()
+    orth = float(np.max(np.abs(V.T @ V - np.eye(r))))
+    lam = np.einsum("kc,kl,lc->c", V, G, V)
+    resid = float(np.max(np.linalg.norm(G @ V - V * lam, axis=0)) / lam_ref[0])
+    e_lam = float(np.max(np.abs(np.sort(lam)[::-1] - lam_ref)) / lam_ref[0])
+    rot_err = float(np.max(np.abs(Mp.double().cpu().numpy() - M.astype(np.float64) @ V)) /
+                    np.max(np.abs(M)))
+    print(f"{kind} K={K} r={r}: orthogonality {orth:.1e}, residual {resid:.1e}, "
+          f"eigenvalues {e_lam:.1e}, M V_r {rot_err:.1e}", flush=True)
+    assert orth < 1e-6 and resid < 1e-12 and e_lam < 1e-12 and rot_err < 1e-5
+    f.close()
