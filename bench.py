@@ -41,6 +41,8 @@ BLOCK_SIZES = (8, 32)      # actions per round of the block-residual policy timi
 SAMPLE_PATHS = 32          # paths per call of the path-sampler timing
 SAMPLE_STEPS = 20          # steps of the path-sampler timing
 SYM_STRIDE = 16            # timed steps: every 16th action-loop matvec launch is timed
+LARGE_WARMUP = 5      # steps before the timed ones on the largest workload
+LARGE_STEPS = 3
 GRAD_WARMUP_STEPS = 6      # untimed derivative pass before the timed one (truncation included)
 
 
@@ -199,7 +201,11 @@ def next_rows(seed=0):
       * the filter and the computation-aware RTS smoother (Alg. 3) on the n = 16384
         great-circle workload (Matern-3/2, m = 4096, i = 64, r = 256), T = 100;
       * the path sampler (App. C) on the same workload, SAMPLE_PATHS paths over the first
-        SAMPLE_STEPS steps, forward and backward."""
+        SAMPLE_STEPS steps, forward and backward;
+      * the filter on the largest workload (n = 262144, Matern-3/2, m = 32768 of the 90%
+        of locations ever observed, i = 256 CG actions, r = 1024, BF16X3 block product):
+        steps/s over LARGE_STEPS steps after LARGE_WARMUP steps (the warm-up grows the factor
+        to 1280 columns, so every timed step truncates 1280 -> 1024), with its phases."""
     import torch
     from paper_2405_08971_amd.autograd import loglik
     from paper_2405_08971_amd.filter import CAKF, Record
@@ -328,6 +334,21 @@ def next_rows(seed=0):
         "backward_ms_per_step": (t2 - t1) * 1e3 / (T - 1),
         "note": "prior draws from the random-Fourier-feature surrogate (2048 features)"}
     del fwd, xs_f, w_f, qs, es
+    torch.cuda.empty_cache()
+    cfg = CONFIGS["sphere_n262144"]
+    wl = Workload(cfg, seed=seed)
+    X = torch.from_numpy(wl.X.astype(np.float32)).cuda()
+    inputs = device_inputs(wl, range(1, LARGE_WARMUP + LARGE_STEPS + 2))
+    r = run(cfg, X, inputs, LARGE_WARMUP, LARGE_STEPS, "bf16x3", breakdown=1)
+    out["large"] = {
+        "workload": f"{cfg.name}: n={cfg.n} Fibonacci-sphere points, Matern-{cfg.nu2}/2 "
+                    f"chordal, m={cfg.m} (10% of locations never observed), i={cfg.i} CG "
+                    f"actions, r={cfg.r}, bf16x3",
+        "value": LARGE_STEPS / r["elapsed"], "unit": "steps/s",
+        "ms_per_step": r["elapsed"] / LARGE_STEPS * 1e3,
+        "phases_ms_per_step": r["phases"], "dropped_actions": r["dropped"],
+        "nonfinite": r["nonfinite"]}
+    del r, inputs, X
     torch.cuda.empty_cache()
     return out
 

@@ -246,8 +246,9 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
 constexpr double TRI_CTOL = 1e-13;
 constexpr int TRI_ITERS = 3;
 constexpr int TRI_MAXK = 1280;         // LDS of the cluster kernel (6 K doubles)
-constexpr int TW_VPB = 8;              // eigenvectors per workgroup of the twisted kernel
-constexpr int TW_MAXK = 640;           // LDS of the twisted kernel (3 TW_VPB K doubles)
+// the twisted kernel keeps 3 VPB K pivots and vector entries in LDS: VPB = 8 eigenvectors
+// per workgroup for K <= 640, 4 for K <= 1280
+constexpr int TW_LDS = 5120;           // VPB * largest K
 
 // Gershgorin bounds of T widened by rounding, ||T|| and the pivot floor, per workgroup.
 __device__ void tri_bounds(const double* __restrict__ d, const double* __restrict__ e, int K,
@@ -368,11 +369,13 @@ __global__ __launch_bounds__(256) void k_tri_bisect(const double* __restrict__ d
 // forward factorisation of eigenvector v and lane 2v + 1 the backward one, the pivots
 // kept in LDS; the twist index is chosen by the whole wave, then the same two lanes
 // extend z below and above it, and the wave normalises.
+template <int TW_VPB>
 __global__ __launch_bounds__(64) void k_tri_twisted(const double* __restrict__ d,
                                                     const double* __restrict__ e, int K, int r,
                                                     const double* __restrict__ lam,
                                                     const double* __restrict__ info,
                                                     double* __restrict__ Zr) {
+    constexpr int TW_MAXK = TW_LDS / TW_VPB;
     __shared__ double dl[TW_MAXK], el[TW_MAXK];
     __shared__ double Dv[TW_VPB][TW_MAXK], Dpv[TW_VPB][TW_MAXK], zv[TW_VPB][TW_MAXK];
     __shared__ int kb_s[TW_VPB];
@@ -608,15 +611,19 @@ __global__ __launch_bounds__(64) void k_tri_clusters(const double* __restrict__ 
 }
 
 int tri_eigen_work_elems(int K, int r) { return r + 2; }
-int tri_eigen_max_k() { return TW_MAXK; }
+int tri_eigen_max_k() { return TW_LDS / 4; }
 
 void launch_tri_eigen(const double* d, const double* e, int K, int r, double* work, double* Zr,
                       hipStream_t st) {
     double* lam = work;
     double* info = work + r;
     hipLaunchKernelGGL(k_tri_bisect, dim3((r + 3) / 4), dim3(256), 0, st, d, e, K, r, lam, info);
-    hipLaunchKernelGGL(k_tri_twisted, dim3((r + TW_VPB - 1) / TW_VPB), dim3(64), 0, st, d, e, K,
-                       r, lam, info, Zr);
+    if (K <= TW_LDS / 8)
+        hipLaunchKernelGGL(k_tri_twisted<8>, dim3((r + 7) / 8), dim3(64), 0, st, d, e, K, r, lam,
+                           info, Zr);
+    else
+        hipLaunchKernelGGL(k_tri_twisted<4>, dim3((r + 3) / 4), dim3(64), 0, st, d, e, K, r, lam,
+                           info, Zr);
     hipLaunchKernelGGL(k_tri_clusters, dim3(32), dim3(64), 0, st, d, e, K, r, lam, info, Zr);
 }
 
@@ -733,7 +740,8 @@ void launch_backtransform(const double* Z, long long zrs, long long zcs, const d
     else if (u <= 4) CAKF_BT(4);
     else if (u <= 6) CAKF_BT(6);
     else if (u <= 8) CAKF_BT(8);
-    else CAKF_BT(10);
+    else if (u <= 10) CAKF_BT(10);
+    else CAKF_BT(20);
 #undef CAKF_BT
 }
 

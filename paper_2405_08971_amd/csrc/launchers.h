@@ -148,7 +148,7 @@ void launch_smooth_messages(const float* Bs, int ldb, int n, const int32_t* idx,
 void launch_pad_points(const float4* Xs, int n, int np, float4* Xp, hipStream_t st);
 
 // ---- eig.hip
-constexpr int TD_MAXK = 640;        // largest K of the one-launch tridiagonalisation
+constexpr int TD_MAXK = 1280;       // largest K of the one-launch tridiagonalisation
 int tridiag_max_k();
 int tridiag_workgroups(int K);
 hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double* d, double* e,

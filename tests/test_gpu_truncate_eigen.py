@@ -24,9 +24,12 @@ def _spectrum(kind, K, r):
     return np.sort(s)[::-1]
 
 
-@pytest.mark.parametrize("kind", ["distinct", "near_pairs", "tie_across_cutoff", "two_blocks",
-                                  "all_equal"])
-@pytest.mark.parametrize("K,r", [(64, 48), (190, 170)])
+KINDS = ["distinct", "near_pairs", "tie_across_cutoff", "two_blocks", "all_equal"]
+CASES = ([(k, 64, 48) for k in KINDS] + [(k, 190, 170) for k in KINDS] +
+         [(k, 1280, 1024) for k in ("distinct", "tie_across_cutoff")])
+
+
+@pytest.mark.parametrize("kind,K,r", CASES)
 def test_truncation_eigenvectors(kind, K, r):
     import torch
     from paper_2405_08971_amd.filter import CAKF
