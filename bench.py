@@ -75,6 +75,10 @@ def parse():
                    help="instead of the benchmark: run both modes with their own CG actions "
                         "for this many steps beside the FP64 oracle replaying each run's "
                         "actions (minutes of host time), print the per-step errors")
+    p.add_argument("--oracle-timing", action="store_true",
+                   help="instead of the benchmark: time the FP64 oracle (host only) on the "
+                        "planned workloads: n = 1024 and the n = 16384 great-circle filter at "
+                        "full length with CG actions, the first 6 steps of n = 65536")
     p.add_argument("--replay-steps", type=int, default=200,
                    help="steps of the BF16X3-vs-FP32 replay with shared CG actions")
     return p.parse_args()
@@ -571,6 +575,52 @@ def fp64_horizon(cfg, X, wl, T):
     return out
 
 
+ORACLE_TIMING = (("plane_n1024", None), ("sphere_gc_n16384", None), ("sphere_n65536", 6))
+
+
+def oracle_timing():
+    """The FP64 oracle (plain NumPy, CG actions, the iterative update of App. B, then the
+    truncation of Sec. 3.2) timed on the host's cores: kernel products spread over a pool of
+    threads, BLAS over the same number.  Per workload: seconds per step over the steps run
+    (full length, or the first steps of the largest), the host model and thread count."""
+    from oracle.cakf import Model, run_filter
+    from paper_2405_08971_amd.workload import CONFIGS, Workload
+    threads = max(1, min(16, os.cpu_count() or 1))
+    os.environ["ORACLE_THREADS"] = str(threads)
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(threads)
+    except Exception:
+        pass
+    try:
+        model_name = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                           if ln.startswith("model name")), "unknown")
+    except OSError:
+        model_name = "unknown"
+    out = {"host": model_name, "threads": threads, "workloads": {}}
+    for name, T in ORACLE_TIMING:
+        cfg = CONFIGS[name]
+        T = cfg.T if T is None else T
+        wl = Workload(cfg, seed=0)
+        model = Model(wl.X.astype(np.float32).astype(np.float64), cfg.nu2, cfg.ell,
+                      cfg.sigma_f2, cfg.a, cfg.noise_var, cfg.dist)
+        m0 = M0 = None
+        t0 = time.perf_counter()
+        for k in range(1, T + 1):
+            idx, y = wl.step(k)
+            rec, = run_filter(model, [(idx.astype(np.int64),
+                                       y.astype(np.float32).astype(np.float64))],
+                              cfg.i, cfg.r, policy="cg", m0=m0, M0=M0)
+            m0, M0 = rec.m, rec.M_plus
+            if k % 10 == 0 or k == T:
+                print(f"{name}: step {k}/{T} ({time.perf_counter() - t0:.0f} s)",
+                      file=sys.stderr, flush=True)
+        el = time.perf_counter() - t0
+        out["workloads"][name] = {"steps": T, "seconds": el, "s_per_step": el / T,
+                                  "n": cfg.n, "m": cfg.m, "i": cfg.i, "r": cfg.r}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -583,6 +633,9 @@ def main():
         return
     if args.rate_probe:
         rate_probe()
+        return
+    if args.oracle_timing:
+        print(json.dumps({"oracle_timing": oracle_timing()}), flush=True)
         return
     import torch
     from paper_2405_08971_amd.workload import CONFIGS, Workload
