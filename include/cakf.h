@@ -403,9 +403,10 @@ int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double dt
 
 /* Phases timed by the profiling hooks (HIP events on the context stream around each
  * launch of the phase). */
-#define CAKF_PHASE_SYM_TILES     0   /* kernel-matrix x action matvec of the action loop */
-#define CAKF_PHASE_FORM_U        1   /* tile reduction and Gram partial sums             */
-#define CAKF_PHASE_TAIL          2   /* FP64 incremental Cholesky                        */
+#define CAKF_PHASE_SYM_TILES     0   /* one action of the loop: kernel-matrix x action   */
+                                     /* matvec, its reduction and the FP64 Cholesky step */
+#define CAKF_PHASE_FORM_U        1   /* (no separate launch: part of SYM_TILES)          */
+#define CAKF_PHASE_TAIL          2   /* FP64 Cholesky steps of a block-policy round      */
 #define CAKF_PHASE_NEXT_ACTION   3   /* CG residual = next action                        */
 #define CAKF_PHASE_BLOCK_PRODUCT 4   /* kernel-matrix x [W w] block product               */
 #define CAKF_PHASE_GRAM          5   /* FP64 Gram matrix of the factor                   */

@@ -67,8 +67,13 @@ struct cakf_ctx {
     float* part;
     double* cpart;     // next_action's per-block column products
     double* colvec;    // the reduced column products of the current action
-    double* fupart;    // form_u's per-block partial sums of s_j^T u_j
-    double* ttpart;
+    double* fupart;    // per-row-block sums of s_j^T u_j (action-loop step)
+    double* tri;       // triangular products of the current action's Cholesky step
+    unsigned* ctr;     // arrival counter of the sym_tiles spare blocks (zero between launches)
+    double* ttpart;    // the spare blocks' shares of T^T t_j
+    double* beta2;     // beta after odd actions (c->beta: after even actions, and final)
+    double* SS;        // S^T S of the current update's actions (rows l <= j)
+    double* SSwork;    // its factorisation once the loop ends, when too large for LDS
     float* mpart;
     double *Linv, *LinvT, *L, *LSinv, *LSinvT, *alpha, *beta;
     LoopState* ls;
@@ -195,7 +200,7 @@ void prof_free(cakf_ctx* c) {
 
 static void free_all(cakf_ctx* c) {
     void* ptrs[] = {c->mean, c->M[0], c->M[1], c->Xs, c->Xo, c->r0, c->Mo, c->S, c->U, c->V, c->T,
-                    c->part, c->cpart, c->colvec, c->fupart, c->ttpart, c->mpart, c->Linv,
+                    c->part, c->cpart, c->colvec, c->fupart, c->tri, c->ctr, c->ttpart, c->beta2, c->SS, c->SSwork, c->mpart, c->Linv,
                     c->LinvT, c->L, c->LSinv, c->LSinvT,
                     c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->Bth, c->Btl, c->G, c->gwork, c->eigval,
                     c->offdiag, c->info, c->Vr, c->tdV, c->tdtau, c->tdp, c->tdrow, c->tdctr,
@@ -357,8 +362,13 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     rc |= dalloc(&c->part, (size_t)nbmax * c->mpmax);
     rc |= dalloc(&c->cpart, (size_t)nablk * c->gs);
     rc |= dalloc(&c->colvec, (size_t)c->gs);
-    rc |= dalloc(&c->fupart, (size_t)(c->mpmax / 64));
-    rc |= dalloc(&c->ttpart, (size_t)c->imax);
+    rc |= dalloc(&c->fupart, (size_t)nbmax);
+    rc |= dalloc(&c->tri, (size_t)tri_elems(c->imax));
+    rc |= dalloc(&c->ctr, 1);
+    rc |= dalloc(&c->ttpart, (size_t)((c->ldmo + 31) / 32) * c->imax);
+    rc |= dalloc(&c->beta2, c->imax);
+    rc |= dalloc(&c->SS, (size_t)c->imax * c->imax);
+    rc |= dalloc(&c->SSwork, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->mpart, (size_t)std::max(nablk, (c->mmax + 63) / 64) * c->ldmo);
     rc |= dalloc(&c->Linv, (size_t)c->imax * c->imax);
     rc |= dalloc(&c->LinvT, (size_t)c->imax * c->imax);
@@ -517,6 +527,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     if (c->Xp) launch_pad_points(c->Xs, c->n, c->np, c->Xp, c->stream);
     if (hipMemsetAsync(c->mean, 0, (size_t)c->N * sizeof(float), c->stream) != hipSuccess ||
         hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ctr, 0, sizeof(unsigned), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         rocblas_destroy_handle(c->blas);
         free_all(c);
@@ -657,9 +668,9 @@ static int block_rounds(cakf_ctx* c, const ObsDims& d, int imax, hipStream_t st)
             td.sc = bt;
             td.vc = 2 * bt;
             td.rc = 3 * bt;
-            launch_tail(nullptr, nullptr, 0, nullptr, d, j0, c->cfg.noise_var,
-                        c->cfg.resid_tol, c->cfg.pivot_tol, c->Linv, c->LinvT, c->L, c->LSinv,
-                        c->LSinvT, c->alpha, c->beta, c->ls, st, td, bt);
+            launch_tail(d, j0, c->cfg.noise_var, c->cfg.resid_tol, c->cfg.pivot_tol, c->Linv,
+                        c->LinvT, c->L, c->LSinv, c->LSinvT, c->alpha, c->beta, c->ls, st, td,
+                        bt);
         }
         j0 += bt;
     }
@@ -717,32 +728,57 @@ extern "C" int cakf_update(cakf_ctx* c, const int32_t* idx, const float* y, int 
     // column products of s_0
     int ncp = 0, nmpart = 0;
     if (!block)
-        launch_next_action(0, 0, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise, d, 0,
-                           c->mpart, c->cpart, c->gs, c->ls, st, &ncp);
+        launch_next_action(0, 0, c->U, c->Mo, c->r0, c->S, c->V, c->T, noise, d, 0, c->mpart,
+                           c->cpart, c->gs, c->ls, nullptr, st, &ncp);
+    TriArgs ta;
+    ta.Linv = c->Linv;
+    ta.LinvT = c->LinvT;
+    ta.alpha = c->alpha;
+    ta.tri = c->tri;
+    ta.ctr = c->ctr;
+    ta.ttpart = c->ttpart;
+    ta.noise_var = c->cfg.noise_var;
+    // beta after action j lives in bbuf[j & 1]
+    double* bbuf[2] = {c->beta, c->beta2};
+    TailArgs tl;
+    tl.imax = d.imax;
+    tl.tri = c->tri;
+    tl.colvec = c->colvec;
+    tl.fupart = c->fupart;
+    tl.Linv = c->Linv;
+    tl.LinvT = c->LinvT;
+    tl.L = c->L;
+    tl.alpha = c->alpha;
+    tl.SS = c->SS;
+    tl.noise_var = c->cfg.noise_var;
+    tl.resid_tol = c->cfg.resid_tol;
+    tl.pivot_tol = c->cfg.pivot_tol;
     for (int j = 0; j < (block ? 0 : imax); ++j) {
         {
             KernelTimer t(c, CAKF_PHASE_SYM_TILES);
             launch_sym_tiles(nu2, dist, c->cfg.prec != CAKF_PREC_FP32, c->Xo, c->S, d, j,
                              c->part, (j > 0 && d.rank > 0) ? c->mpart : nullptr, nmpart,
-                             c->T, c->cpart, ncp, c->gs, c->colvec, c->ls, st, t.start, t.stop);
+                             c->T, c->cpart, ncp, c->gs, c->colvec, c->ls, ta, st, t.start,
+                             t.stop);
         }
         int nfu = 0;
         {
             PhaseTimer t(c, CAKF_PHASE_FORM_U);
-            launch_form_u(c->part, c->S, c->U, c->T, d, j, c->cfg.signal_var, c->fupart,
-                          c->ttpart, c->ls, st, &nfu);
+            launch_form_u(c->part, c->S, c->U, d, j, c->cfg.signal_var, c->fupart, c->ls, st,
+                          &nfu);
         }
-        {
-            PhaseTimer t(c, CAKF_PHASE_TAIL);
-            launch_tail(c->colvec, c->fupart, nfu, c->ttpart, d, j, c->cfg.noise_var,
-                        c->cfg.resid_tol, c->cfg.pivot_tol, c->Linv, c->LinvT, c->L, c->LSinv,
-                        c->LSinvT, c->alpha, c->beta, c->ls, st);
-        }
+        tl.nfu = nfu;
+        tl.beta_in = bbuf[(j + 1) & 1];
+        tl.beta_out = bbuf[j & 1];
         if (j + 1 < imax) {
+            // the rest of action j's Cholesky step, then action j + 1
             PhaseTimer t(c, CAKF_PHASE_NEXT_ACTION);
-            launch_next_action(cg ? 1 : 0, 1, c->U, c->Mo, c->r0, c->S, c->V, c->beta, c->T, noise,
-                               d, j + 1, c->mpart, c->cpart, c->gs, c->ls, st, &ncp);
+            launch_next_action(cg ? 1 : 0, 1, c->U, c->Mo, c->r0, c->S, c->V, c->T, noise, d,
+                               j + 1, c->mpart, c->cpart, c->gs, c->ls, &tl, st, &ncp);
             nmpart = ncp;
+        } else {
+            PhaseTimer t(c, CAKF_PHASE_TAIL);
+            launch_tail_final(tl, j, c->beta2, c->beta, c->SSwork, c->ls, st);
         }
     }
     launch_build_block(c->S, c->LinvT, c->beta, d, c->B, c->bp, c->bp, rec->W_obs, rec->w_obs,

@@ -21,7 +21,7 @@ constexpr int next_action_blocks(int m, int cpl, int lpl) {
 // Direct mode of the Cholesky step (block-residual rounds): the Gram columns of the
 // actions come ready from a round's product G (ld columns; row l = action l): columns
 // uc + g, sc + g, vc + g hold s_l^T u_g, s_l^T s_g, s_l^T v_g of the round's action g,
-// column rc holds s_l^T r0.  G == nullptr selects the column products of the CG loop.
+// column rc holds s_l^T r0.
 struct TailDirect {
     const double* G = nullptr;
     int ld = 0, uc = 0, sc = 0, vc = 0, rc = 0;
@@ -50,21 +50,73 @@ void launch_colsum_partial(const float* A, int lda, int rows, int cols, const fl
                            int ldx, float* partial, int ldp, hipStream_t st, int* nblk_out);
 void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, float* out,
                          int ldo, hipStream_t st);
-// mfma_dist: Euclidean Matern-3/2 and -5/2 take the squared distances from FP32 MFMA
-// (dot-product form); otherwise every entry uses the difference form on the VALU.
+// Offsets in the buffer of triangular products of an action's Cholesky step
+// (tri_elems(imax) doubles): lrow and nrow (imax each), then the scalars l2 = |lrow|^2,
+// la = lrow^T alpha and t_j^T t_j.
+__host__ __device__ constexpr int tri_lrow(int imax) { return 0 * imax; }
+__host__ __device__ constexpr int tri_nrow(int imax) { return 1 * imax; }
+__host__ __device__ constexpr int tri_scal(int imax) { return 2 * imax; }
+__host__ __device__ constexpr int tri_elems(int imax) { return 2 * imax + 3; }
+
+// Inputs and outputs of the triangular products, taken by the last spare block of an
+// action's sym_tiles launch: L^{-1} and its transpose (FP64, row-major, ld imax), alpha,
+// the spare blocks' shares of T^T t_j (ceil(ldmo / 32) x imax doubles), the output
+// buffer and the launch's arrival counter (one word, zero between launches; every launch
+// leaves it at zero).
+struct TriArgs {
+    double* ttpart = nullptr;
+    const double* Linv = nullptr;
+    const double* LinvT = nullptr;
+    const double* alpha = nullptr;
+    double* tri = nullptr;
+    unsigned* ctr = nullptr;
+    double noise_var = 0.0;
+};
+
+// The O(j) rest of the Cholesky step of action j (obs_loop.hip): form_u's per-block sums
+// of s_j^T u_j, the triangular products, the column products of s_j, beta after action
+// j - 1 (beta_in) and the buffer for beta after action j (beta_out, another buffer), the
+// rows it extends, the Gram matrix S^T S it fills (row j: s_l^T s_j, l <= j; its log
+// determinant is taken once the loop ends), and the loop's tolerances.
+struct TailArgs {
+    const double* fupart = nullptr;
+    int nfu = 0;
+    int imax = 0;
+    const double* tri = nullptr;
+    const double* colvec = nullptr;
+    const double* beta_in = nullptr;
+    double* beta_out = nullptr;
+    double* Linv = nullptr;
+    double* LinvT = nullptr;
+    double* L = nullptr;
+    double* alpha = nullptr;
+    double* SS = nullptr;
+    double noise_var = 0.0, resid_tol = 0.0, pivot_tol = 0.0;
+};
+
+// The action-loop matvec of action j (sym_tiles.hip).  mfma_dist: Euclidean Matern-3/2
+// and -5/2 take the squared distances from FP32 MFMA (dot-product form); otherwise every
+// entry uses the difference form on the VALU.
 void launch_sym_tiles(int nu2, int dist, bool mfma_dist, const float4* Xo, const float* S,
                       const ObsDims& d, int j, float* part, const float* mpart, int nmpart,
                       float* T, const double* cpart, int ncpart, int gs, double* colvec,
-                      const LoopState* ls, hipStream_t st, hipEvent_t ev_start = nullptr,
-                      hipEvent_t ev_stop = nullptr);
-void launch_form_u(const float* part, const float* S, float* U, const float* T,
-                   const ObsDims& d, int j, double sigma_f2, double* fupart, double* ttv,
-                   const LoopState* ls, hipStream_t st, int* nblk_out);
-void launch_tail(const double* colvec, const double* fupart, int nfu, const double* ttv,
-                 const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
-                 double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
-                 double* alpha, double* beta, LoopState* ls, hipStream_t st,
-                 const TailDirect& td = TailDirect{}, int nj = 1);
+                      const LoopState* ls, const TriArgs& ta, hipStream_t st,
+                      hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// u_j = sum of the tile sums into U[:, j], and per-block sums of s_j^T u_j
+void launch_form_u(const float* part, const float* S, float* U, const ObsDims& d, int j,
+                   double sigma_f2, double* fupart, const LoopState* ls, hipStream_t st,
+                   int* nblk_out);
+// the step of the last action (no next action follows), the final beta into beta_final
+// (beta_odd: the buffer of the odd actions), and the log determinant of S^T S over the
+// kept actions with the log-likelihood term (work: imax x imax doubles)
+void launch_tail_final(const TailArgs& ta, int j, const double* beta_odd, double* beta_final,
+                       double* work, LoopState* ls, hipStream_t st);
+// The Cholesky steps of a block-policy round (direct mode, td.G != nullptr): nj actions
+// from jfirst on.
+void launch_tail(const ObsDims& d, int jfirst, double noise_var, double resid_tol,
+                 double pivot_tol, double* Linv, double* LinvT, double* L, double* LSinv,
+                 double* LSinvT, double* alpha, double* beta, LoopState* ls, hipStream_t st,
+                 const TailDirect& td, int nj);
 void launch_block_residual(const float* U, const float* V, float* S, const float* r0,
                            const double* beta, float noise_var, const ObsDims& d, int j0, int bt,
                            const LoopState* ls, hipStream_t st);
@@ -84,11 +136,11 @@ void launch_round_mot(const float* Mo, const float* S, const ObsDims& d, int j0,
 // resid: the CG residual is the action (else the action is read from S); mopart: also form
 // the per-block partial sums of Mo^T s_jt (always with resid), finished by the next
 // sym_tiles launch into column jt of T
+// ta: the Cholesky step of action jt - 1 to finish first (required with resid)
 void launch_next_action(int resid, int mopart, const float* U, const float* Mo,
-                        const float* r0, float* S, float* V, const double* beta,
-                        const float* T, float noise_var, const ObsDims& d, int jt,
-                        float* mpart, double* cpart, int gs, const LoopState* ls,
-                        hipStream_t st, int* nblk_out);
+                        const float* r0, float* S, float* V, const float* T, float noise_var,
+                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
+                        LoopState* ls, const TailArgs* ta, hipStream_t st, int* nblk_out);
 void launch_build_block(const float* S, const double* LinvT, const double* beta,
                         const ObsDims& d, float* B, int ldb, int bp, float* rec_W,
                         float* rec_w, float* rec_S, const LoopState* ls, hipStream_t st);

@@ -18,12 +18,16 @@
 // s_l^T s_j for l < j, and s_j^T s_j, r0^T s_j, is formed from rows that are already
 // loaded when s_j is produced.  One iteration j launches:
 //   sym_tiles    u_j tile sums; its first blocks finish the column products of s_j
-//                (and, CG, t_j = Mo^T s_j) from the previous launch's block partials
+//                (and, CG, t_j = Mo^T s_j) from the previous launch's block partials;
+//                through arrival counters, the last tile of each row block forms those
+//                rows of u_j (and of s_j^T u_j), the last spare block the triangular
+//                products of the Cholesky step, and the last arrival of all the FP64
+//                Cholesky step itself: column j of C, row j of L^{-1}, alpha and beta
 //                (sym_tiles.hip);
-//   form_u       u_j = sum of the tile sums, and the partial sums of s_j^T u_j;
-//   tail         one FP64 block: column j of C, the Cholesky step, alpha and beta;
 //   next_action  CG: s_{j+1} = the residual, V[:, j] = Mo t_j, partial sums of
 //                Mo^T s_{j+1}; both policies: the column products of s_{j+1}.
+// The block-residual policy forms the Gram columns of a round of actions in one product
+// instead and takes the round's Cholesky steps in one launch of the tail kernel.
 #include "cakf_common.h"
 #include "launchers.h"
 
@@ -181,65 +185,26 @@ void launch_colsum_final(const float* partial, int ldp, int nblk, int cols, floa
 
 // ------------------------------------------------------------------------- form_u
 // u_j[p] = sigma_f2 * (sum over the nb slots of the tile partial sums, FP64), stored in
-// U[:, j], and per-block partial sums (FP64) of s_j^T u_j, FU_ROWS rows per block.  The
-// TT_COLS-wide column blocks after the row blocks compute (T^T t_j)_l = t_l^T t_j for
-// l <= j (FP64), one wave per column group.
+// U[:, j], and per-block partial sums (FP64) of s_j^T u_j, FU_ROWS rows per block.
 constexpr int FU_ROWS = 64;
 constexpr int FU_LOADS = 8;
-constexpr int TT_COLS = 16;
 
 __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
                                                 const float* __restrict__ S,
-                                                float* __restrict__ U,
-                                                const float* __restrict__ T, ObsDims d,
-                                                int j, double sigma_f2, int n_rowblk,
-                                                double* __restrict__ fupart,
-                                                double* __restrict__ ttv,
+                                                float* __restrict__ U, ObsDims d, int j,
+                                                double sigma_f2, double* __restrict__ fupart,
                                                 const LoopState* __restrict__ ls) {
     if (ls->stop) return;
-    const int tid = threadIdx.x;
-    const int J = j + 1;
-    if ((int)blockIdx.x >= n_rowblk) {
-        // (T^T t_j)_l for l in this block's TT_COLS columns, 4 per wave; the loads of a
-        // batch of 8 factor-column groups are issued before any product
-        const int lane = tid & 63, w = tid >> 6;
-        const int l0 = (blockIdx.x - n_rowblk) * TT_COLS + w * (TT_COLS / 4);
-        const float* tj = T + (size_t)j * d.ldmo;
-        double acc[TT_COLS / 4];
-#pragma unroll
-        for (int u = 0; u < TT_COLS / 4; ++u) acc[u] = 0.0;
-        for (int c0 = 0; c0 < d.rank; c0 += 8 * 64) {
-            float tv[8], tl[TT_COLS / 4][8];
-#pragma unroll
-            for (int g = 0; g < 8; ++g) {
-                const int c = c0 + 64 * g + lane;
-                tv[g] = c < d.rank ? tj[c] : 0.0f;
-#pragma unroll
-                for (int u = 0; u < TT_COLS / 4; ++u) {
-                    const int l = l0 + u;
-                    tl[u][g] = (l < J && c < d.rank) ? T[(size_t)l * d.ldmo + c] : 0.0f;
-                }
-            }
-#pragma unroll
-            for (int g = 0; g < 8; ++g)
-#pragma unroll
-                for (int u = 0; u < TT_COLS / 4; ++u)
-                    acc[u] = __builtin_fma((double)tl[u][g], (double)tv[g], acc[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < TT_COLS / 4; ++u) {
-            const double v = wave_sum(acc[u]);
-            if (lane == 0 && l0 + u < J) ttv[l0 + u] = v;
-        }
-        return;
-    }
-    // rows: thread (quad, grp) sums rows 4 quad .. 4 quad + 3 of the block over the slots
-    // grp, grp + 16, ... with 16-byte loads, FU_LOADS slots in flight at a time; the 16
-    // slot groups are then combined in a fixed order
+    // thread (quad, grp) sums rows 4 quad .. 4 quad + 3 of the block over the slots grp,
+    // grp + 16, ... with 16-byte loads, FU_LOADS slots in flight at a time; the 16 slot
+    // groups are then combined in a fixed order
     __shared__ double ured[16][FU_ROWS + 1];
+    const int tid = threadIdx.x;
     const int nb = d.mp / SYM_TILE;
     const int quad = tid & 15, grp = tid >> 4;
     const int p0 = blockIdx.x * FU_ROWS + 4 * quad;    // < mp (mp a multiple of 128)
+    const int prow = blockIdx.x * FU_ROWS + tid;
+    const float sj = (tid < FU_ROWS && prow < d.m) ? S[(size_t)prow * d.imax + j] : 0.0f;
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
     for (int s0 = grp; s0 < nb; s0 += 16 * FU_LOADS) {
         float4 v[FU_LOADS];
@@ -261,34 +226,177 @@ __global__ __launch_bounds__(256) void k_form_u(const float* __restrict__ part,
     for (int r = 0; r < 4; ++r) ured[grp][4 * quad + r] = a4[r];
     __syncthreads();
     if (tid < FU_ROWS) {
-        const int p = blockIdx.x * FU_ROWS + tid;
         double t = 0.0;
 #pragma unroll
         for (int g = 0; g < 16; ++g) t += ured[g][tid];
         double prod = 0.0;
-        if (p < d.m) {
+        if (prow < d.m) {
             const float uf = (float)(sigma_f2 * t);
-            U[(size_t)p * d.imax + j] = uf;
-            prod = (double)S[(size_t)p * d.imax + j] * (double)uf;
+            U[(size_t)prow * d.imax + j] = uf;
+            prod = (double)sj * (double)uf;
         }
         prod = wave_sum(prod);
         if (tid == 0) fupart[blockIdx.x] = prod;
     }
 }
 
-void launch_form_u(const float* part, const float* S, float* U, const float* T,
-                   const ObsDims& d, int j, double sigma_f2, double* fupart, double* ttv,
-                   const LoopState* ls, hipStream_t st, int* nblk_out) {
+void launch_form_u(const float* part, const float* S, float* U, const ObsDims& d, int j,
+                   double sigma_f2, double* fupart, const LoopState* ls, hipStream_t st,
+                   int* nblk_out) {
     const int rowblk = (d.m + FU_ROWS - 1) / FU_ROWS;
-    const int ttblk = d.rank > 0 ? (j + 1 + TT_COLS - 1) / TT_COLS : 0;
     *nblk_out = rowblk;
-    hipLaunchKernelGGL(k_form_u, dim3(rowblk + ttblk), dim3(256), 0, st, part, S, U, T, d, j,
-                       sigma_f2, rowblk, fupart, ttv, ls);
+    hipLaunchKernelGGL(k_form_u, dim3(rowblk), dim3(256), 0, st, part, S, U, d, j, sigma_f2,
+                       fupart, ls);
+}
+
+// ---------------------------------------------------------------- Cholesky step, O(j)
+// The rest of the Cholesky step of action j once u_j and the triangular products are
+// formed: C_jj = s_j^T u_j + noise_var s_j^T s_j - t_j^T t_j, the pivot
+// d^2 = C_jj - |lrow|^2 (breakdown stops the loop and drops the action),
+// alpha_j = (r0^T s_j - lrow^T alpha) / d, row j of L (lrow, d) and of L^{-1}
+// (-nrow / d, 1 / d), beta_j = beta_{j-1} + alpha_j (row j of L^{-1}); the
+// residual-tolerance stop.  Every wave of every block that takes it computes the same
+// scalars (the same loads, sums in a fixed order).
+struct TailScalars {
+    double inv_d, aj, dj;
+    int verdict;      // 0: keep action j; 1: tolerance stop; 2: breakdown; 3: non-finite
+};
+
+__device__ TailScalars tail_scalars(const TailArgs& ta, int j, const LoopState* ls) {
+    const int lane = threadIdx.x & 63, ld = ta.imax;
+    double fu = 0.0;
+    for (int b = lane; b < ta.nfu; b += 64) fu += ta.fupart[b];
+    fu = wave_sum(fu);
+    const double* tri = ta.tri;
+    const double qjj = ta.colvec[2 * j], c_j = ta.colvec[2 * j + 1];
+    const double l2 = tri[tri_scal(ld)], la = tri[tri_scal(ld) + 1];
+    const double cjj = fu - tri[tri_scal(ld) + 2] + ta.noise_var * qjj;
+    TailScalars r{0.0, 0.0, 0.0, 0};
+    if (j > 0 && ta.resid_tol > 0.0 && qjj <= ta.resid_tol * ta.resid_tol * ls->q00) {
+        r.verdict = 1;
+        return r;
+    }
+    const double d2 = cjj - l2;
+    const bool finite = isfinite(d2) && isfinite(cjj);
+    if (!(finite && d2 > ta.pivot_tol * cjj && d2 > 0.0)) {
+        r.verdict = finite ? 2 : 3;
+        return r;
+    }
+    r.dj = sqrt(d2);
+    r.inv_d = 1.0 / r.dj;
+    r.aj = (c_j - la) * r.inv_d;
+    return r;
+}
+
+// entry l <= j of row j of L^{-1} and of beta_j
+__device__ __forceinline__ double tail_linv(const TailArgs& ta, const TailScalars& ts, int j,
+                                            int l) {
+    return l < j ? -ta.tri[tri_nrow(ta.imax) + l] * ts.inv_d : ts.inv_d;
+}
+
+__device__ __forceinline__ double tail_beta(const TailArgs& ta, const TailScalars& ts, int j,
+                                            int l) {
+    const double prev = l < j ? ta.beta_in[l] : 0.0;
+    return __builtin_fma(ts.aj, tail_linv(ta, ts, j, l), prev);
+}
+
+// The stores of the step (one workgroup of at least j + 1 threads, the same scalars in
+// every thread): the loop state, and for a kept action row j of L, L^{-1}, S^T S,
+// alpha_j and beta_j (into beta_out).
+__device__ void tail_store(const TailArgs& ta, const TailScalars& ts, int j, LoopState* ls) {
+    const int tid = threadIdx.x, ld = ta.imax, J = j + 1;
+    if (ts.verdict != 0) {
+        if (tid == 0) {
+            ls->stop = 1;
+            if (ts.verdict >= 2) ls->dropped += 1;
+            if (ts.verdict == 3) ls->nonfinite += 1;
+        }
+        return;
+    }
+    if (tid < J) {
+        const double v = tail_linv(ta, ts, j, tid);
+        ta.Linv[(size_t)j * ld + tid] = v;
+        ta.LinvT[(size_t)tid * ld + j] = v;
+        ta.L[(size_t)j * ld + tid] = tid < j ? ta.tri[tri_lrow(ld) + tid] : ts.dj;
+        ta.SS[(size_t)j * ld + tid] = ta.colvec[j + tid];
+        ta.beta_out[tid] = tail_beta(ta, ts, j, tid);
+    }
+    if (tid == 0) {
+        if (j == 0) ls->q00 = ta.colvec[0];
+        ta.alpha[j] = ts.aj;
+        ls->logdet_c += 2.0 * log(ts.dj);
+        ls->alpha2 += ts.aj * ts.aj;
+        ls->i_eff = J;
+    }
+}
+
+// After the loop (one workgroup of 256 threads): the step of the last action when the
+// loop ran to it (no next action follows), the final beta into beta_final when the last
+// kept action left it in the other buffer, then log det S^T S over the kept actions
+// (right-looking Cholesky of the leading block, FP64; pivots floored at 1e-300 as in the
+// block-policy step) and the projected log-likelihood term
+//     -1/2 (i log 2 pi + log det S^T Ghat S - log det S^T S + |L^{-1} S^T r0|^2).
+// The factorisation runs in LDS up to TF_LDS_N actions (row stride TF_LDS_N + 1 doubles,
+// so that a column's entries fall in different banks) and in work (imax^2 doubles) above;
+// the pivots are kept and their logs summed at the end.
+constexpr int TF_LDS_N = 128;
+
+__global__ __launch_bounds__(256) void k_tail_final(TailArgs ta, int j,
+                                                    const double* __restrict__ beta_odd,
+                                                    double* __restrict__ beta_final,
+                                                    double* __restrict__ work,
+                                                    LoopState* __restrict__ ls) {
+    __shared__ double Al[TF_LDS_N * (TF_LDS_N + 1)];
+    __shared__ double piv[256];
+    __shared__ double red[4];
+    const int tid = threadIdx.x, ld = ta.imax;
+    if (!ls->stop) {
+        const TailScalars ts = tail_scalars(ta, j, ls);
+        tail_store(ta, ts, j, ls);
+    }
+    __syncthreads();
+    const int ie = ls->i_eff;
+    if (ie > 0 && ((ie - 1) & 1))
+        for (int l = tid; l < ie; l += 256) beta_final[l] = beta_odd[l];
+    double* A = ie <= TF_LDS_N ? Al : work;
+    const int la = ie <= TF_LDS_N ? TF_LDS_N + 1 : ld;
+    for (int i = tid / 16; i < ie; i += 16)
+        for (int l = tid % 16; l <= i; l += 16) A[i * la + l] = ta.SS[(size_t)i * ld + l];
+    __syncthreads();
+    for (int k = 0; k < ie; ++k) {
+        const double dk = sqrt(fmax(A[k * la + k], 1e-300));
+        const double rk = 1.0 / dk;
+        if (tid == 0) piv[k] = dk;
+        for (int i = k + 1 + tid; i < ie; i += 256) A[i * la + k] *= rk;
+        __syncthreads();
+        for (int i = k + 1 + tid / 16; i < ie; i += 16) {
+            const double aik = A[i * la + k];
+            for (int l = k + 1 + tid % 16; l <= i; l += 16) A[i * la + l] -= aik * A[l * la + k];
+        }
+        __syncthreads();
+    }
+    double lg = tid < ie ? 2.0 * log(piv[tid]) : 0.0;
+    lg = wave_sum(lg);
+    if ((tid & 63) == 0) red[tid >> 6] = lg;
+    __syncthreads();
+    if (tid == 0) {
+        const double logdet = (red[0] + red[1]) + (red[2] + red[3]);
+        ls->logdet_s = logdet;
+        ls->loglik = -0.5 * ((double)ie * 1.8378770664093453 + ls->logdet_c - logdet +
+                             ls->alpha2);
+    }
+}
+
+void launch_tail_final(const TailArgs& ta, int j, const double* beta_odd, double* beta_final,
+                       double* work, LoopState* ls, hipStream_t st) {
+    hipLaunchKernelGGL(k_tail_final, dim3(1), dim3(256), 0, st, ta, j, beta_odd, beta_final,
+                       work, ls);
 }
 
 // --------------------------------------------------------------------------- tail
-// One block of 1024 threads, FP64.  Assembles column j of C = S^T Ghat S from the
-// column products, extends its Cholesky factor C = L L^T (L^{-1} kept explicitly,
+// The Cholesky steps of a block-policy round: one block of 1024 threads, FP64, actions
+// jfirst .. jfirst + nj - 1 in turn.  Takes column j of C = S^T Ghat S from the round's
+// Gram product, extends its Cholesky factor C = L L^T (L^{-1} kept explicitly,
 // row-major Linv and column-major LinvT so that every triangular product reads
 // coalesced), alpha = L^{-1} S^T r0, beta = L^{-T} alpha (updated in place: the new row
 // of L^{-1} times alpha_j is all that changes), the Cholesky factor of S^T S (log det
@@ -332,11 +440,7 @@ __device__ __forceinline__ int pow2_at_least(int v) {
     return p;
 }
 
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict__ colvec,
-                                                       const double* __restrict__ fupart,
-                                                       int nfu,
-                                                       const double* __restrict__ ttv,
-                                                       ObsDims d, int jfirst, double noise_var,
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(ObsDims d, int jfirst, double noise_var,
                                                        double resid_tol, double pivot_tol,
                                                        double* __restrict__ Linv,
                                                        double* __restrict__ LinvT,
@@ -352,38 +456,27 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
     const int tid = threadIdx.x;
     if (ls->stop) return;
     const int ld = d.imax;
-    // nj consecutive actions jfirst .. jfirst + nj - 1 (nj > 1 only in direct mode); every
-    // exit below is taken by the whole workgroup and ends the loop with the stop flag set
+    // every exit below is taken by the whole workgroup and ends the loop with the stop
+    // flag set
     const double* gdir = td.G;
     for (int g = 0; g < nj; ++g) {
         const int j = jfirst + g;
         const int J = j + 1;
-        // 1. column j: u_l^T s_j (l < j) and s_l^T s_j (l <= j) from the column products,
-        //    s_j^T u_j from form_u's partial sums
-        //    (direct mode: s_l^T u_j, s_l^T s_j, s_l^T v_j and s_j^T r0 from columns
-        //    uc + g, sc + g, vc + g and rc of td.G)
-        double fu = 0.0, cj = 0.0, unused = 0.0;
-        if (!gdir)
-            for (int b = tid; b < nfu; b += TAIL_THREADS) fu += fupart[b];
-        if (tid == 0) cj = gdir ? gdir[(size_t)j * td.ld + td.rc] : colvec[2 * j + 1];
-        double gcol = 0.0, qcol = 0.0, tt = 0.0, al = 0.0;
+        // 1. column j: s_l^T u_j, s_l^T s_j, s_l^T v_j and s_j^T r0 from columns uc + g,
+        //    sc + g, vc + g and rc of td.G
+        double cj = 0.0, unused0 = 0.0, unused1 = 0.0;
+        if (tid == 0) cj = gdir[(size_t)j * td.ld + td.rc];
+        double gcol = 0.0, qcol = 0.0, al = 0.0;
         if (tid < J) {
-            if (gdir) {
-                const double* row = gdir + (size_t)tid * td.ld;
-                qcol = row[td.sc + g];
-                gcol = row[td.uc + g] + noise_var * qcol - row[td.vc + g];
-            } else {
-                gcol = tid < j ? colvec[tid] : 0.0;
-                qcol = colvec[j + tid];
-                tt = d.rank > 0 ? ttv[tid] : 0.0;
-            }
+            const double* row = gdir + (size_t)tid * td.ld;
+            qcol = row[td.sc + g];
+            gcol = row[td.uc + g] + noise_var * qcol - row[td.vc + g];
             al = tid < j ? alpha[tid] : 0.0;
         }
-        block_sum3(fu, cj, unused, red);
+        block_sum3(cj, unused0, unused1, red);
         const double c_j = cj;
         if (tid < J) {
-            const double gv = (gdir || tid < j) ? gcol : fu;
-            Ccol[tid] = gdir ? gv : gv - tt + noise_var * qcol;
+            Ccol[tid] = gcol;
             Qcol[tid] = qcol;
             alph[tid] = al;
         }
@@ -508,14 +601,13 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(const double* __restrict_
     }
 }
 
-void launch_tail(const double* colvec, const double* fupart, int nfu, const double* ttv,
-                 const ObsDims& d, int j, double noise_var, double resid_tol, double pivot_tol,
-                 double* Linv, double* LinvT, double* L, double* LSinv, double* LSinvT,
-                 double* alpha, double* beta, LoopState* ls, hipStream_t st,
+void launch_tail(const ObsDims& d, int jfirst, double noise_var, double resid_tol,
+                 double pivot_tol, double* Linv, double* LinvT, double* L, double* LSinv,
+                 double* LSinvT, double* alpha, double* beta, LoopState* ls, hipStream_t st,
                  const TailDirect& td, int nj) {
-    hipLaunchKernelGGL(k_tail, dim3(1), dim3(TAIL_THREADS), 0, st, colvec, fupart, nfu, ttv, d,
-                       j, noise_var, resid_tol, pivot_tol, Linv, LinvT, L, LSinv, LSinvT, alpha,
-                       beta, ls, td, td.G ? nj : 1);
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(TAIL_THREADS), 0, st, d, jfirst, noise_var,
+                       resid_tol, pivot_tol, Linv, LinvT, L, LSinv, LSinvT, alpha, beta, ls, td,
+                       nj);
 }
 
 // ---------------------------------------------------------------------- next_action
@@ -523,6 +615,8 @@ void launch_tail(const double* colvec, const double* fupart, int nfu, const doub
 // the per-block partial sums (FP64) of its column products
 //     u_l^T s_jt (l < jt),  s_l^T s_jt (l <= jt),  r0^T s_jt,
 // laid out as [u^T s (jt) | s^T s (jt + 1) | r0^T s] in cpart[block * gs + pos].
+// With tail (jt >= 1) the launch first finishes the Cholesky step of action j = jt - 1
+// (tail_scalars in every wave, tail_store in block 0), and stops on its verdict.
 // RESID, with j = jt - 1: s_jt = r0 - Ghat S beta = r0 - (U - Mo T + noise_var S) beta,
 // the residual after jt actions, stored unnormalised in S[:, jt]; V[:, j] = Mo t_j (the
 // low-rank part kept per row, V = Mo T) and the per-block partial sums of Mo^T s_jt
@@ -535,13 +629,13 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
                                                      const float* __restrict__ r0,
                                                      float* __restrict__ S,
                                                      float* __restrict__ V,
-                                                     const double* __restrict__ beta,
                                                      const float* __restrict__ T,
                                                      float noise_var, ObsDims d, int jt,
                                                      int mopart,
                                                      float* __restrict__ mpart,
                                                      double* __restrict__ cpart, int gs,
-                                                     const LoopState* __restrict__ ls) {
+                                                     LoopState* __restrict__ ls, TailArgs ta,
+                                                     int tail) {
     if (ls->stop) return;
     __shared__ float mred[4][64 * CPL];
     __shared__ double gred[4][64 * LPL], qred[4][64 * LPL];
@@ -549,6 +643,7 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int p0 = (blockIdx.x * 4 + w) * RW;
     const int j = jt - 1;
+    // the O(j) rest of the Cholesky step of action j (every block; block 0 stores it)
     // lowrank: this pass also forms the partial sums of Mo^T s_jt (mopart; the CG residual
     // needs Mo t_j as well)
     const bool lowrank = (RESID || mopart) && d.rank > 0;
@@ -562,13 +657,11 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
     }
 #pragma unroll
     for (int v = 0; v < LPL; ++v) {
-        const int l = lane + 64 * v;
-        bl[v] = (RESID && l <= j) ? (float)beta[l] : 0.0f;
         g[v] = 0.0;
         q[v] = 0.0;
     }
-    const float bj = RESID ? (float)beta[j] : 0.0f;
-    // loads of all RW rows
+    // loads of all RW rows (issued before the Cholesky step's loads and its exit, which
+    // the row loads do not depend on)
     float mo[RW][CPL], uu[RW][LPL], sv[RW][LPL], vv[RW][LPL], r0v[RW], sr[RW];
 #pragma unroll
     for (int b = 0; b < RW; ++b) {
@@ -594,6 +687,18 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
             mo[b][4 * k4 + 3] = x.w;
         }
     }
+    TailScalars ts{0.0, 0.0, 0.0, 0};
+    if (tail) {
+        ts = tail_scalars(ta, j, ls);
+        if (blockIdx.x == 0) tail_store(ta, ts, j, ls);
+        if (ts.verdict != 0) return;
+    }
+#pragma unroll
+    for (int v = 0; v < LPL; ++v) {
+        const int l = lane + 64 * v;
+        bl[v] = (RESID && l <= j) ? (float)tail_beta(ta, ts, j, l) : 0.0f;
+    }
+    const float bj = RESID ? (float)(ts.aj * ts.inv_d) : 0.0f;
     float rho[RW];
     if constexpr (RESID) {
         float dotp[RW], part[RW];
@@ -676,64 +781,65 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
 
 template <bool RESID, int CPL, int LPL>
 static void launch_na(int blocks, const float* U, const float* Mo, const float* r0, float* S,
-                      float* V, const double* beta, const float* T, float noise_var,
-                      const ObsDims& d, int jt, int mopart, float* mpart, double* cpart,
-                      int gs, const LoopState* ls, hipStream_t st) {
+                      float* V, const float* T, float noise_var, const ObsDims& d, int jt,
+                      int mopart, float* mpart, double* cpart, int gs, LoopState* ls,
+                      const TailArgs& ta, int tail, hipStream_t st) {
     constexpr int RW = next_action_rows_per_wave(CPL, LPL);
     hipLaunchKernelGGL((k_next_action<RESID, CPL, LPL, RW>), dim3(blocks), dim3(256), 0, st, U,
-                       Mo, r0, S, V, beta, T, noise_var, d, jt, mopart, mpart, cpart, gs, ls);
+                       Mo, r0, S, V, T, noise_var, d, jt, mopart, mpart, cpart, gs, ls, ta,
+                       tail);
 }
 
 template <bool RESID, int CPL>
 static void launch_na_l(int lpl, int blocks, const float* U, const float* Mo, const float* r0,
-                        float* S, float* V, const double* beta, const float* T, float noise_var,
-                        const ObsDims& d, int jt, int mopart, float* mpart, double* cpart,
-                        int gs, const LoopState* ls, hipStream_t st) {
+                        float* S, float* V, const float* T, float noise_var, const ObsDims& d,
+                        int jt, int mopart, float* mpart, double* cpart, int gs, LoopState* ls,
+                        const TailArgs& ta, int tail, hipStream_t st) {
     if (lpl == 1)
-        launch_na<RESID, CPL, 1>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
-                                 mpart, cpart, gs, ls, st);
+        launch_na<RESID, CPL, 1>(blocks, U, Mo, r0, S, V, T, noise_var, d, jt, mopart, mpart,
+                                 cpart, gs, ls, ta, tail, st);
     else if (lpl == 2)
-        launch_na<RESID, CPL, 2>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
-                                 mpart, cpart, gs, ls, st);
+        launch_na<RESID, CPL, 2>(blocks, U, Mo, r0, S, V, T, noise_var, d, jt, mopart, mpart,
+                                 cpart, gs, ls, ta, tail, st);
     else
-        launch_na<RESID, CPL, 4>(blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
-                                 mpart, cpart, gs, ls, st);
+        launch_na<RESID, CPL, 4>(blocks, U, Mo, r0, S, V, T, noise_var, d, jt, mopart, mpart,
+                                 cpart, gs, ls, ta, tail, st);
 }
 
 template <bool RESID>
 static void launch_na_c(int cpl, int lpl, int blocks, const float* U, const float* Mo,
-                        const float* r0, float* S, float* V, const double* beta,
-                        const float* T, float noise_var, const ObsDims& d, int jt, int mopart,
-                        float* mpart, double* cpart, int gs, const LoopState* ls,
-                        hipStream_t st) {
+                        const float* r0, float* S, float* V, const float* T, float noise_var,
+                        const ObsDims& d, int jt, int mopart, float* mpart, double* cpart,
+                        int gs, LoopState* ls, const TailArgs& ta, int tail, hipStream_t st) {
     if (cpl == 4)
-        launch_na_l<RESID, 4>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
-                              mpart, cpart, gs, ls, st);
+        launch_na_l<RESID, 4>(lpl, blocks, U, Mo, r0, S, V, T, noise_var, d, jt, mopart, mpart,
+                              cpart, gs, ls, ta, tail, st);
     else if (cpl == 8)
-        launch_na_l<RESID, 8>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
-                              mpart, cpart, gs, ls, st);
+        launch_na_l<RESID, 8>(lpl, blocks, U, Mo, r0, S, V, T, noise_var, d, jt, mopart, mpart,
+                              cpart, gs, ls, ta, tail, st);
     else
-        launch_na_l<RESID, 16>(lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, mopart,
-                               mpart, cpart, gs, ls, st);
+        launch_na_l<RESID, 16>(lpl, blocks, U, Mo, r0, S, V, T, noise_var, d, jt, mopart, mpart,
+                               cpart, gs, ls, ta, tail, st);
 }
 
 void launch_next_action(int resid, int mopart, const float* U, const float* Mo,
-                        const float* r0, float* S, float* V, const double* beta,
-                        const float* T, float noise_var, const ObsDims& d, int jt,
-                        float* mpart, double* cpart, int gs, const LoopState* ls,
-                        hipStream_t st, int* nblk_out) {
+                        const float* r0, float* S, float* V, const float* T, float noise_var,
+                        const ObsDims& d, int jt, float* mpart, double* cpart, int gs,
+                        LoopState* ls, const TailArgs* ta, hipStream_t st, int* nblk_out) {
     // the lanes cover the factor columns whenever Mo is read (CG residual or mopart)
     const bool reads_mo = (resid || mopart) && d.rank > 0;
     const int lpl = next_action_lpl(d.imax);
     const int cpl = reads_mo ? next_action_cpl(d.ldmo) : 4;
     const int blocks = next_action_blocks(d.m, cpl, lpl);
     *nblk_out = blocks;
+    const TailArgs none{};
+    const int tail = ta != nullptr ? 1 : 0;
     if (resid)
-        launch_na_c<true>(cpl, lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt, 1,
-                          mpart, cpart, gs, ls, st);
+        launch_na_c<true>(cpl, lpl, blocks, U, Mo, r0, S, V, T, noise_var, d, jt, 1, mpart,
+                          cpart, gs, ls, tail ? *ta : none, tail, st);
     else
-        launch_na_c<false>(cpl, lpl, blocks, U, Mo, r0, S, V, beta, T, noise_var, d, jt,
-                           mopart ? 1 : 0, mpart, cpart, gs, ls, st);
+        launch_na_c<false>(cpl, lpl, blocks, U, Mo, r0, S, V, T, noise_var, d, jt,
+                           mopart ? 1 : 0, mpart, cpart, gs, ls, tail ? *ta : none, tail, st);
 }
 
 // ------------------------------------------------------------------ block-residual policy

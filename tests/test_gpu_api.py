@@ -78,14 +78,15 @@ def test_profile_stride_times_every_kth_launch():
     cfg = small_config("stride", n=300, m=60, i=8, r=20, T=2)
     X, steps, _ = inputs(cfg, seed=94, policy="cg")
     f = _filter(cfg, X)
-    # one update runs i = 8 action-loop matvecs: every 3rd of them is timed (0, 3, 6)
-    f.profile(["sym_tiles", "tail"], every=3)
+    # one update runs i = 8 action steps and 7 next-action launches: every 3rd of each is
+    # timed (0, 3, 6)
+    f.profile(["sym_tiles", "next_action"], every=3)
     idx, y = steps[0]
     f.step(torch.from_numpy(idx).cuda(), torch.from_numpy(y).cuda())
     prof = f.profile_read()
-    assert prof["sym_tiles"][1] == 3 and prof["tail"][1] == 3
+    assert prof["sym_tiles"][1] == 3 and prof["next_action"][1] == 3
     assert prof["sym_tiles"][0] > 0.0
-    assert prof["form_u"][1] == 0                      # not enabled
+    assert prof["gram"][1] == 0                        # not enabled
     # reading resets the counters and the sampling phase
     f.profile(["sym_tiles"], every=1)
     idx, y = steps[1]
