@@ -2,21 +2,21 @@
 // cooperative launch), the first stage of the symmetric eigensolver behind Truncate
 // (Sec. 3.2): G = Q T Q^T with T tridiagonal, Q = H_0 H_1 ... H_{K-3},
 // H_j = I - tau_j v_j v_j^T, and the back-transformation Q Z of the leading
-// eigenvectors of T.  The tridiagonal eigenproblem itself (divide and conquer) is a
-// rocSOLVER call made by the host.
+// eigenvectors of T.
 //
 // Why one launch: the reduction is a chain of K - 2 dependent steps, each a symmetric
 // matrix-vector product with the trailing matrix and a rank-2 update.  As separate
 // kernels every step costs several launches; here the K x K matrix is distributed by
-// rows over the LDS of a few workgroups (row i lives in workgroup i mod G), each step's
-// matrix work is local, and the workgroups exchange only two vectors per step through
-// global memory, separated by one grid-wide barrier:
-//   after barrier j every workgroup holds v_j, tau_j and reads p_j = tau_j A v_j (each
-//   owner wrote its rows' entries) and row j+1 of the matrix before update j (written by
-//   its owner); it forms w_j = p_j - (tau_j / 2)(p_j^T v_j) v_j, the updated row j+1
+// rows over the registers of a few workgroups (row i lives in workgroup i mod G, lane l
+// of the owning wave holds its entries l + 64 t), each step's matrix work is local, and
+// the workgroups exchange only two vectors per step through global memory, separated by
+// one grid-wide barrier:
+//   after barrier j every wave holds v_j, tau_j and reads p_j = tau_j A v_j (each owner
+//   wrote its rows' entries) and row j+1 of the matrix before update j (written by its
+//   owner); it forms w_j = p_j - (tau_j / 2)(p_j^T v_j) v_j, the updated row j+1
 //   (row - v_{j+1} w_j - w_{j+1} v_j) and from it v_{j+1}, tau_{j+1} (identically in
-//   every workgroup: same data, same reduction order); then one pass over its own rows
-//   applies update j and forms its rows of p_{j+1}; the owner of row j+2 publishes it.
+//   every wave: same data, same reduction order); then it applies update j to its own
+//   rows and forms their entries of p_{j+1}; the owner of row j+2 publishes it.
 // Vectors are double-buffered by the parity of j, so a workgroup one step ahead never
 // overwrites what a slower one still reads.  The reflector of step j follows LAPACK's
 // convention (dlarfg: v_j[j+1] = 1, beta = -sign(alpha) ||x||).
@@ -33,25 +33,20 @@
 
 namespace cakf {
 
-constexpr int TD_THREADS = 512;
-constexpr int TD_LDS = 12800;           // doubles of matrix rows per workgroup (100 KiB)
-
 int tridiag_max_k() { return TD_MAXK; }
 
-int tridiag_workgroups(int K) {
-    const int rows = TD_LDS / K;
-    return (K + rows - 1) / rows;
-}
+// Shapes of the register-resident reduction: KC column chunks of 64 per row, WAVES waves
+// per workgroup, R rows per wave (the rows and four chunked vectors stay in registers).
+template <int KC, int WAVES, int R>
+struct TdShape {
+    static constexpr int kc = KC, waves = WAVES, rows = R;
+    static int workgroups(int K) { return (K + WAVES * R - 1) / (WAVES * R); }
+};
+using TdSmall = TdShape<10, 8, 5>;     // K <= 640: 40 rows per workgroup
+using TdLarge = TdShape<20, 4, 3>;     // K <= 1280: 12 rows per workgroup
 
-__device__ __forceinline__ double td_block_sum(double v, double* red) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < TD_THREADS / 64; ++w) s += red[w];
-    __syncthreads();
-    return s;
+int tridiag_workgroups(int K) {
+    return K <= 64 * TdSmall::kc ? TdSmall::workgroups(K) : TdLarge::workgroups(K);
 }
 
 // The arrival is a release (the workgroup's writes, ordered before it by the block
@@ -79,7 +74,8 @@ __device__ __forceinline__ void td_barrier(unsigned* ctr, unsigned target, int* 
 // G: K x K symmetric (both triangles).  Out: V (column-major K x K; column j holds v_j
 // in rows j+2 .. K-1), tau, d (K), e (K - 1).  pbuf, rowbuf: 2K doubles each; ctr and
 // abort_flag zero on entry.
-__global__ __launch_bounds__(TD_THREADS) void k_tridiag(const double* __restrict__ G, int K,
+template <int KC, int WAVES, int R>
+__global__ __launch_bounds__(WAVES * 64) void k_tridiag(const double* __restrict__ G, int K,
                                                         double* __restrict__ V,
                                                         double* __restrict__ tau,
                                                         double* __restrict__ d,
@@ -87,74 +83,114 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const double* __restrict
                                                         double* __restrict__ pbuf,
                                                         double* __restrict__ rowbuf,
                                                         unsigned* ctr, int* abort_flag) {
-    __shared__ double Al[TD_LDS];
-    __shared__ double xr[TD_MAXK], vv[TD_MAXK], ww[TD_MAXK];
-    __shared__ double red[TD_THREADS / 64];
+    // LDS copies of v (by parity), w and the new row, for the lookups of single entries
+    __shared__ double vs[2][64 * KC], ws[64 * KC], xs[64 * KC];
     const int NWG = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int nloc = (K - wg + NWG - 1) / NWG;      // rows wg, wg + NWG, ...
-    for (int rr = wave; rr < nloc; rr += TD_THREADS / 64)
-        for (int k = lane; k < K; k += 64) Al[rr * K + k] = G[(size_t)(wg + rr * NWG) * K + k];
-    for (int k = tid; k < K; k += TD_THREADS) xr[k] = G[k];
-    __syncthreads();
+    double a[R][KC];
+    int rowi[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const int i = wg + (wave + WAVES * s) * NWG;
+        rowi[s] = i < K ? i : -1;
+#pragma unroll
+        for (int t = 0; t < KC; ++t) {
+            const int k = lane + 64 * t;
+            a[s][t] = (i < K && k < K) ? G[(size_t)i * K + k] : 0.0;
+        }
+    }
     // reflector of column 0 from row 0
-    double tj = 0.0;
+    double v[KC], w[KC];
+    double tj;
     {
-        double s = 0.0;
-        for (int k = 2 + tid; k < K; k += TD_THREADS) s += xr[k] * xr[k];
-        const double xn2 = td_block_sum(s, red);
-        const double alpha = xr[1];
+        double x[KC], s2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < KC; ++t) {
+            const int k = lane + 64 * t;
+            x[t] = k < K ? G[k] : 0.0;
+            if (k >= 2) s2 += x[t] * x[t];
+        }
+        const double xn2 = wave_sum(s2);
+        const double alpha = G[1];
         double beta = alpha, scale = 0.0;
+        tj = 0.0;
         if (xn2 != 0.0) {
             beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
             tj = (beta - alpha) / beta;
             scale = 1.0 / (alpha - beta);
         }
-        for (int k = 1 + tid; k < K; k += TD_THREADS) vv[k] = (k == 1) ? 1.0 : xr[k] * scale;
+#pragma unroll
+        for (int t = 0; t < KC; ++t) {
+            const int k = lane + 64 * t;
+            v[t] = k == 1 ? 1.0 : (k > 1 ? x[t] * scale : 0.0);
+        }
         if (wg == 0 && tid == 0) {
-            d[0] = xr[0];
+            d[0] = G[0];
             e[0] = beta;
             tau[0] = tj;
         }
-        __syncthreads();
     }
-    for (int rr = wave; rr < nloc; rr += TD_THREADS / 64) {
-        const int i = wg + rr * NWG;
+    if (wave == 0)
+#pragma unroll
+        for (int t = 0; t < KC; ++t) vs[0][lane + 64 * t] = v[t];
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
         double acc = 0.0;
-        if (i > 0)
-            for (int k = 1 + lane; k < K; k += 64) acc += Al[rr * K + k] * vv[k];
+#pragma unroll
+        for (int t = 0; t < KC; ++t) acc += a[s][t] * v[t];
         acc = wave_sum(acc);
-        if (lane == 0 && i > 0) pbuf[i] = tj * acc;
+        if (lane == 0 && rowi[s] > 0) pbuf[rowi[s]] = tj * acc;
+        if (rowi[s] == 1)
+#pragma unroll
+            for (int t = 0; t < KC; ++t) {
+                const int k = lane + 64 * t;
+                if (k >= 1 && k < K) rowbuf[k] = a[s][t];
+            }
     }
-    if (1 % NWG == wg)
-        for (int k = 1 + tid; k < K; k += TD_THREADS) rowbuf[k] = Al[(1 / NWG) * K + k];
     for (int j = 0; j < K - 2; ++j) {
         const int b = j & 1;
-        // v_j into column j of V, spread over the workgroups
-        for (int k = j + 2 + wg * TD_THREADS + tid; k < K; k += NWG * TD_THREADS)
-            V[(size_t)j * K + k] = vv[k];
+        // v_j into column j of V (one workgroup per step)
+        if (wg == j % NWG && wave == 0)
+#pragma unroll
+            for (int t = 0; t < KC; ++t) {
+                const int k = lane + 64 * t;
+                if (k >= j + 2 && k < K) V[(size_t)j * K + k] = v[t];
+            }
         td_barrier(ctr, (unsigned)(j + 1) * NWG, abort_flag);
-        double s2 = 0.0;
-        for (int k = j + 1 + tid; k < K; k += TD_THREADS) {
-            const double pk = pbuf[b * K + k];
-            ww[k] = pk;
-            xr[k] = rowbuf[b * K + k];
-            s2 += pk * vv[k];
+        const double* pb = pbuf + b * K;
+        const double* rb = rowbuf + b * K;
+        double x[KC], s2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < KC; ++t) {
+            const int k = lane + 64 * t;
+            const bool in = k > j && k < K;
+            const double pk = in ? pb[k] : 0.0;
+            x[t] = in ? rb[k] : 0.0;
+            w[t] = pk;
+            s2 += pk * v[t];
         }
-        const double kk = 0.5 * tj * td_block_sum(s2, red);
-        for (int k = j + 1 + tid; k < K; k += TD_THREADS) ww[k] -= kk * vv[k];
+        const double kk = 0.5 * tj * wave_sum(s2);
+        // w_{j+1} = p_{j+1} - kk (v_j[j+1] = 1)
+        const double w1 = pb[j + 1] - kk;
+        double sx = 0.0;
+#pragma unroll
+        for (int t = 0; t < KC; ++t) {
+            const int k = lane + 64 * t;
+            w[t] -= kk * v[t];
+            // row j+1 after update j
+            x[t] = k > j ? x[t] - w[t] - w1 * v[t] : 0.0;
+            if (k >= j + 3) sx += x[t] * x[t];
+        }
+        const double xn2 = wave_sum(sx);
+        if (wave == 0)
+#pragma unroll
+            for (int t = 0; t < KC; ++t) {
+                ws[lane + 64 * t] = w[t];
+                xs[lane + 64 * t] = x[t];
+            }
         __syncthreads();
-        // row j+1 after update j (v_j[j+1] = 1), and the reflector of column j+1
-        const double w1 = ww[j + 1];
-        double s = 0.0;
-        for (int k = j + 1 + tid; k < K; k += TD_THREADS) {
-            const double x = xr[k] - ww[k] - w1 * vv[k];
-            xr[k] = x;
-            if (k >= j + 3) s += x * x;
-        }
-        const double xn2 = td_block_sum(s, red);
         const int j1 = j + 1;
-        const double alpha = xr[j1 + 1];
+        const double alpha = xs[j1 + 1];
         double beta = alpha, scale = 0.0, tn = 0.0;
         if (xn2 != 0.0) {
             beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -162,42 +198,59 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const double* __restrict
             scale = 1.0 / (alpha - beta);
         }
         if (wg == 0 && tid == 0) {
-            d[j1] = xr[j1];
+            d[j1] = xs[j1];
             e[j1] = beta;
             tau[j1] = tn;
         }
-        // one pass over the own rows: update j, then this row's entry of p_{j+1}
-        for (int rr = wave; rr < nloc; rr += TD_THREADS / 64) {
-            const int i = wg + rr * NWG;
-            if (i <= j) continue;
-            const double vi = vv[i], wi = ww[i];
+        // the new reflector (into x)
+#pragma unroll
+        for (int t = 0; t < KC; ++t) {
+            const int k = lane + 64 * t;
+            x[t] = k == j1 + 1 ? 1.0 : (k > j1 + 1 ? x[t] * scale : 0.0);
+        }
+        // update j of the own rows, then their entries of p_{j+1}
+        const double* vprev = vs[b];
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int i = rowi[s];
+            if (i <= j) continue;                  // wave-uniform
+            const double vi = vprev[i], wi = ws[i];
             double acc = 0.0;
-            for (int k = j + 1 + lane; k < K; k += 64) {
-                const double a = Al[rr * K + k] - (vi * ww[k] + wi * vv[k]);
-                Al[rr * K + k] = a;
-                if (k > j1) acc += a * ((k == j1 + 1) ? 1.0 : xr[k] * scale);
+#pragma unroll
+            for (int t = 0; t < KC; ++t) {
+                a[s][t] -= vi * w[t] + wi * v[t];
+                acc += a[s][t] * x[t];
             }
             acc = wave_sum(acc);
             if (lane == 0 && i > j1) pbuf[(1 - b) * K + i] = tn * acc;
+            if (i == j1 + 1)
+#pragma unroll
+                for (int t = 0; t < KC; ++t) {
+                    const int k = lane + 64 * t;
+                    if (k >= j1 + 1 && k < K) rowbuf[(1 - b) * K + k] = a[s][t];
+                }
         }
-        if ((j1 + 1) % NWG == wg && j1 + 1 < K) {
-            __syncthreads();
-            const int rr = (j1 + 1) / NWG;
-            for (int k = j1 + 1 + tid; k < K; k += TD_THREADS) rowbuf[(1 - b) * K + k] = Al[rr * K + k];
-        }
-        __syncthreads();
-        for (int k = j1 + 1 + tid; k < K; k += TD_THREADS) vv[k] = (k == j1 + 1) ? 1.0 : xr[k] * scale;
+#pragma unroll
+        for (int t = 0; t < KC; ++t) v[t] = x[t];
+        if (wave == 0)
+#pragma unroll
+            for (int t = 0; t < KC; ++t) vs[1 - b][lane + 64 * t] = v[t];
         tj = tn;
-        __syncthreads();
     }
     const bool failed = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
     if (wg == 0 && tid == 0) {
-        d[K - 2] = failed ? __builtin_nan("") : xr[K - 2];
-        e[K - 2] = failed ? __builtin_nan("") : xr[K - 1];
+        const double dk2 = xs[K - 2], ek2 = xs[K - 1];
+        d[K - 2] = failed ? __builtin_nan("") : dk2;
+        e[K - 2] = failed ? __builtin_nan("") : ek2;
         tau[K - 2] = 0.0;
     }
-    if ((K - 1) % NWG == wg && tid == 0)
-        d[K - 1] = failed ? __builtin_nan("") : Al[((K - 1) / NWG) * K + K - 1];
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+        if (rowi[s] == K - 1)
+#pragma unroll
+            for (int t = 0; t < KC; ++t)
+                if (lane + 64 * t == K - 1) d[K - 1] = failed ? __builtin_nan("") : a[s][t];
 }
 
 // Zero the barrier counter and the abort flag before a launch (a kernel rather than a
@@ -218,8 +271,13 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
     const int nwg = tridiag_workgroups(K);
     void* args[] = {(void*)&G, (void*)&K, (void*)&V, (void*)&tau, (void*)&d, (void*)&e,
                     (void*)&pbuf, (void*)&rowbuf, (void*)&ctr, (void*)&abort_flag};
-    return hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(nwg), dim3(TD_THREADS), args,
-                                      0, st);
+    if (K <= 64 * TdSmall::kc)
+        return hipLaunchCooperativeKernel(
+            (const void*)k_tridiag<TdSmall::kc, TdSmall::waves, TdSmall::rows>, dim3(nwg),
+            dim3(TdSmall::waves * 64), args, 0, st);
+    return hipLaunchCooperativeKernel(
+        (const void*)k_tridiag<TdLarge::kc, TdLarge::waves, TdLarge::rows>, dim3(nwg),
+        dim3(TdLarge::waves * 64), args, 0, st);
 }
 
 // ------------------------------------------------------ tridiagonal eigenproblem (top r)

@@ -330,25 +330,28 @@ __device__ void tail_store(const TailArgs& ta, const TailScalars& ts, int j, Loo
     }
 }
 
-// After the loop (one workgroup of 256 threads): the step of the last action when the
-// loop ran to it (no next action follows), the final beta into beta_final when the last
-// kept action left it in the other buffer, then log det S^T S over the kept actions
+// After the loop (one workgroup of TF_THREADS threads): the step of the last action when
+// the loop ran to it (no next action follows), the final beta into beta_final when the
+// last kept action left it in the other buffer, then log det S^T S over the kept actions
 // (right-looking Cholesky of the leading block, FP64; pivots floored at 1e-300 as in the
 // block-policy step) and the projected log-likelihood term
 //     -1/2 (i log 2 pi + log det S^T Ghat S - log det S^T S + |L^{-1} S^T r0|^2).
 // The factorisation runs in LDS up to TF_LDS_N actions (row stride TF_LDS_N + 1 doubles,
-// so that a column's entries fall in different banks) and in work (imax^2 doubles) above;
-// the pivots are kept and their logs summed at the end.
+// so that a column's entries fall in different banks) and in work (imax^2 doubles) above.
+// Thread (r, c) of a 32 x 32 grid updates the trailing entries (i, l) with i = r (mod 32)
+// and l = c (mod 32), all independent of each other.  The pivots are kept and their logs
+// summed at the end.
 constexpr int TF_LDS_N = 128;
+constexpr int TF_THREADS = 1024;
 
-__global__ __launch_bounds__(256) void k_tail_final(TailArgs ta, int j,
-                                                    const double* __restrict__ beta_odd,
-                                                    double* __restrict__ beta_final,
-                                                    double* __restrict__ work,
-                                                    LoopState* __restrict__ ls) {
+__global__ __launch_bounds__(TF_THREADS) void k_tail_final(TailArgs ta, int j,
+                                                           const double* __restrict__ beta_odd,
+                                                           double* __restrict__ beta_final,
+                                                           double* __restrict__ work,
+                                                           LoopState* __restrict__ ls) {
     __shared__ double Al[TF_LDS_N * (TF_LDS_N + 1)];
     __shared__ double piv[256];
-    __shared__ double red[4];
+    __shared__ double red[TF_THREADS / 64];
     const int tid = threadIdx.x, ld = ta.imax;
     if (!ls->stop) {
         const TailScalars ts = tail_scalars(ta, j, ls);
@@ -357,30 +360,35 @@ __global__ __launch_bounds__(256) void k_tail_final(TailArgs ta, int j,
     __syncthreads();
     const int ie = ls->i_eff;
     if (ie > 0 && ((ie - 1) & 1))
-        for (int l = tid; l < ie; l += 256) beta_final[l] = beta_odd[l];
+        for (int l = tid; l < ie; l += TF_THREADS) beta_final[l] = beta_odd[l];
     double* A = ie <= TF_LDS_N ? Al : work;
     const int la = ie <= TF_LDS_N ? TF_LDS_N + 1 : ld;
-    for (int i = tid / 16; i < ie; i += 16)
-        for (int l = tid % 16; l <= i; l += 16) A[i * la + l] = ta.SS[(size_t)i * ld + l];
+    const int r = tid >> 5, c = tid & 31;
+    for (int i = r; i < ie; i += 32)
+        for (int l = c; l <= i; l += 32) A[i * la + l] = ta.SS[(size_t)i * ld + l];
     __syncthreads();
     for (int k = 0; k < ie; ++k) {
         const double dk = sqrt(fmax(A[k * la + k], 1e-300));
         const double rk = 1.0 / dk;
         if (tid == 0) piv[k] = dk;
-        for (int i = k + 1 + tid; i < ie; i += 256) A[i * la + k] *= rk;
+        // this thread's first trailing row and column (i = r, l = c modulo 32)
+        const int i0 = k + 1 + ((r - (k + 1)) & 31), l0 = k + 1 + ((c - (k + 1)) & 31);
+        for (int i = k + 1 + tid; i < ie; i += TF_THREADS) A[i * la + k] *= rk;
         __syncthreads();
-        for (int i = k + 1 + tid / 16; i < ie; i += 16) {
+        for (int i = i0; i < ie; i += 32) {
             const double aik = A[i * la + k];
-            for (int l = k + 1 + tid % 16; l <= i; l += 16) A[i * la + l] -= aik * A[l * la + k];
+            for (int l = l0; l <= i; l += 32) A[i * la + l] -= aik * A[l * la + k];
         }
         __syncthreads();
     }
-    double lg = tid < ie ? 2.0 * log(piv[tid]) : 0.0;
+    double lg = 0.0;
+    for (int t = tid; t < ie; t += TF_THREADS) lg += 2.0 * log(piv[t]);
     lg = wave_sum(lg);
     if ((tid & 63) == 0) red[tid >> 6] = lg;
     __syncthreads();
     if (tid == 0) {
-        const double logdet = (red[0] + red[1]) + (red[2] + red[3]);
+        double logdet = 0.0;
+        for (int w = 0; w < TF_THREADS / 64; ++w) logdet += red[w];
         ls->logdet_s = logdet;
         ls->loglik = -0.5 * ((double)ie * 1.8378770664093453 + ls->logdet_c - logdet +
                              ls->alpha2);
@@ -389,8 +397,8 @@ __global__ __launch_bounds__(256) void k_tail_final(TailArgs ta, int j,
 
 void launch_tail_final(const TailArgs& ta, int j, const double* beta_odd, double* beta_final,
                        double* work, LoopState* ls, hipStream_t st) {
-    hipLaunchKernelGGL(k_tail_final, dim3(1), dim3(256), 0, st, ta, j, beta_odd, beta_final,
-                       work, ls);
+    hipLaunchKernelGGL(k_tail_final, dim3(1), dim3(TF_THREADS), 0, st, ta, j, beta_odd,
+                       beta_final, work, ls);
 }
 
 // --------------------------------------------------------------------------- tail
