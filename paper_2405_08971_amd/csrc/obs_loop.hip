@@ -344,6 +344,28 @@ __device__ void tail_store(const TailArgs& ta, const TailScalars& ts, int j, Loo
 constexpr int TF_LDS_N = 128;
 constexpr int TF_THREADS = 1024;
 
+// Cholesky pivots of the packed-by-rows lower triangle A (row stride la) of order ie, in
+// place (A in LDS or in global memory: one instantiation each, so that the accesses are
+// of that memory's own kind).
+template <typename Ptr>
+__device__ void tf_cholesky(Ptr A, int la, int ie, double* piv) {
+    const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
+    for (int k = 0; k < ie; ++k) {
+        const double dk = sqrt(fmax(A[k * la + k], 1e-300));
+        const double rk = 1.0 / dk;
+        if (tid == 0) piv[k] = dk;
+        // this thread's first trailing row and column (i = r, l = c modulo 32)
+        const int i0 = k + 1 + ((r - (k + 1)) & 31), l0 = k + 1 + ((c - (k + 1)) & 31);
+        for (int i = k + 1 + tid; i < ie; i += TF_THREADS) A[i * la + k] *= rk;
+        __syncthreads();
+        for (int i = i0; i < ie; i += 32) {
+            const double aik = A[i * la + k];
+            for (int l = l0; l <= i; l += 32) A[i * la + l] -= aik * A[l * la + k];
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(TF_THREADS) void k_tail_final(TailArgs ta, int j,
                                                            const double* __restrict__ beta_odd,
                                                            double* __restrict__ beta_final,
@@ -361,25 +383,18 @@ __global__ __launch_bounds__(TF_THREADS) void k_tail_final(TailArgs ta, int j,
     const int ie = ls->i_eff;
     if (ie > 0 && ((ie - 1) & 1))
         for (int l = tid; l < ie; l += TF_THREADS) beta_final[l] = beta_odd[l];
-    double* A = ie <= TF_LDS_N ? Al : work;
-    const int la = ie <= TF_LDS_N ? TF_LDS_N + 1 : ld;
     const int r = tid >> 5, c = tid & 31;
-    for (int i = r; i < ie; i += 32)
-        for (int l = c; l <= i; l += 32) A[i * la + l] = ta.SS[(size_t)i * ld + l];
-    __syncthreads();
-    for (int k = 0; k < ie; ++k) {
-        const double dk = sqrt(fmax(A[k * la + k], 1e-300));
-        const double rk = 1.0 / dk;
-        if (tid == 0) piv[k] = dk;
-        // this thread's first trailing row and column (i = r, l = c modulo 32)
-        const int i0 = k + 1 + ((r - (k + 1)) & 31), l0 = k + 1 + ((c - (k + 1)) & 31);
-        for (int i = k + 1 + tid; i < ie; i += TF_THREADS) A[i * la + k] *= rk;
+    if (ie <= TF_LDS_N) {
+        constexpr int la = TF_LDS_N + 1;
+        for (int i = r; i < ie; i += 32)
+            for (int l = c; l <= i; l += 32) Al[i * la + l] = ta.SS[(size_t)i * ld + l];
         __syncthreads();
-        for (int i = i0; i < ie; i += 32) {
-            const double aik = A[i * la + k];
-            for (int l = l0; l <= i; l += 32) A[i * la + l] -= aik * A[l * la + k];
-        }
+        tf_cholesky(Al, la, ie, piv);
+    } else {
+        for (int i = r; i < ie; i += 32)
+            for (int l = c; l <= i; l += 32) work[i * ld + l] = ta.SS[(size_t)i * ld + l];
         __syncthreads();
+        tf_cholesky(work, ld, ie, piv);
     }
     double lg = 0.0;
     for (int t = tid; t < ie; t += TF_THREADS) lg += 2.0 * log(piv[t]);
