@@ -285,7 +285,7 @@ hipError_t launch_tridiag(const double* G, int K, double* V, double* tau, double
 // computed independently of one another:
 //   eigenvalues  by bisection on Sturm counts (the number of negative pivots of the
 //                LDL^T factorisation of T - sigma I is the number of eigenvalues below
-//                sigma), one wave per eigenvalue; each lane follows four shifts at once,
+//                sigma), two waves per eigenvalue; each lane follows two shifts at once,
 //                so a round tests 256 shifts and shrinks the bracket 257-fold;
 //   eigenvectors by the twisted factorisation of T - lambda I: the forward factor
 //                L D L^T and the backward factor U D' U^T meet at the index k where the
@@ -354,19 +354,25 @@ __device__ __forceinline__ double tri_rcp(double q) {
     return __builtin_fma(__builtin_fma(-q, r, 1.0), r, r);
 }
 
-// One Sturm step: the next pivot, floored at -pivmin when it is too small.
-__device__ __forceinline__ double tri_pivot(double dmin, double e2, double q, double pivmin) {
-    const double v = __builtin_fma(-e2, tri_rcp(q), dmin);
+// One Sturm step of the bisection: the reciprocal estimate with one Newton step (the
+// count needs the pivots' signs; one step leaves them accurate to a few ulp).
+__device__ __forceinline__ double bis_pivot(double dmin, double e2, double q, double pivmin) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = __builtin_fma(__builtin_fma(-q, r, 1.0), r, r);
+    const double v = __builtin_fma(-e2, r, dmin);
     return fabs(v) < pivmin ? -pivmin : v;
 }
 
-// lam[c] (c < r) = the c-th largest eigenvalue; info[0..1] = ||T||, pivot floor.
+// lam[c] (c < r) = the c-th largest eigenvalue; info[0..1] = ||T||, pivot floor.  Two
+// eigenvalues per workgroup, two waves per eigenvalue, two shifts per lane: a round tests
+// 256 shifts and shrinks the bracket 257-fold; the two waves meet in LDS once per round.
 __global__ __launch_bounds__(256) void k_tri_bisect(const double* __restrict__ d,
                                                     const double* __restrict__ e, int K, int r,
                                                     double* __restrict__ lam,
                                                     double* __restrict__ info) {
     __shared__ double dl[TRI_MAXK], e2[TRI_MAXK];
     __shared__ double red[12];
+    __shared__ int pick[4];
     for (int i = threadIdx.x; i < K; i += blockDim.x) {
         dl[i] = d[i];
         e2[i] = i + 1 < K ? e[i] * e[i] : 0.0;
@@ -377,50 +383,58 @@ __global__ __launch_bounds__(256) void k_tri_bisect(const double* __restrict__ d
         info[0] = tnorm;
         info[1] = pivmin;
     }
-    const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= r) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int pair = w >> 1, half = w & 1;
+    const int c = blockIdx.x * 2 + pair;
+    const bool live = c < r;
     const int t = K - 1 - c;                 // ascending index of the eigenvalue
     double lo = glo, hi = ghi;
     // to an absolute accuracy of about eps ||T|| (the accuracy to which the Householder
     // reduction determines the eigenvalues of the Gram matrix)
     const double abstol = 2.220446049250313e-16 * tnorm + pivmin;
     for (int round = 0; round < 12; ++round) {
-        if (hi - lo <= 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + abstol) break;
-        // shifts g = 4 lane + s, s = 0..3, at lo + (hi - lo) (g + 1) / 257
+        const bool done =
+            !live || hi - lo <= 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + abstol;
         const double h = (hi - lo) / 257.0;
-        double sg[4], q[4];
-        int cnt[4];
+        int gw = 128;                        // this wave's first shift above t, of 128
+        if (!done) {
+            // shifts g = 128 half + 2 lane + u, u = 0, 1, at lo + (hi - lo) (g + 1) / 257
+            double sg[2], q[2];
+            int cnt[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            sg[u] = lo + h * (double)(4 * lane + u + 1);
-            q[u] = dl[0] - sg[u];
-            if (fabs(q[u]) < pivmin) q[u] = -pivmin;
-            cnt[u] = q[u] < 0.0;
-        }
-        for (int i = 1; i < K; ++i) {
-            const double di = dl[i], ei = e2[i - 1];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                q[u] = tri_pivot(di - sg[u], ei, q[u], pivmin);
-                cnt[u] += q[u] < 0.0;
+            for (int u = 0; u < 2; ++u) {
+                sg[u] = lo + h * (double)(128 * half + 2 * lane + u + 1);
+                q[u] = dl[0] - sg[u];
+                if (fabs(q[u]) < pivmin) q[u] = -pivmin;
+                cnt[u] = q[u] < 0.0;
             }
-        }
-        // the first shift with more than t eigenvalues below it
-        int first = 4;
+            for (int i = 1; i < K; ++i) {
+                const double di = dl[i], ei = e2[i - 1];
 #pragma unroll
-        for (int u = 3; u >= 0; --u)
-            if (cnt[u] >= t + 1) first = u;
-        const unsigned long long above = __ballot(first < 4);
-        const int l = above ? __builtin_ctzll(above) : 64;
-        const int fl = l < 64 ? __shfl(first, l, 64) : 4;
-        const int g = l < 64 ? 4 * l + fl : 256;          // 0..256
-        const double nlo = g == 0 ? lo : lo + h * (double)g;
-        const double nhi = g == 256 ? hi : lo + h * (double)(g + 1);
-        lo = nlo;
-        hi = nhi;
+                for (int u = 0; u < 2; ++u) {
+                    q[u] = bis_pivot(di - sg[u], ei, q[u], pivmin);
+                    cnt[u] += q[u] < 0.0;
+                }
+            }
+            const int first = cnt[0] >= t + 1 ? 0 : (cnt[1] >= t + 1 ? 1 : 2);
+            const unsigned long long above = __ballot(first < 2);
+            const int l = above ? __builtin_ctzll(above) : 64;
+            const int fl = l < 64 ? __shfl(first, l, 64) : 2;
+            gw = l < 64 ? 2 * l + fl : 128;
+        }
+        if (lane == 0) pick[w] = gw;
+        __syncthreads();
+        const int g0 = pick[2 * pair], g1 = pick[2 * pair + 1];
+        __syncthreads();
+        if (!done) {
+            const int g = g0 < 128 ? g0 : (g1 < 128 ? 128 + g1 : 256);   // 0..256
+            const double nlo = g == 0 ? lo : lo + h * (double)g;
+            const double nhi = g == 256 ? hi : lo + h * (double)(g + 1);
+            lo = nlo;
+            hi = nhi;
+        }
     }
-    if (lane == 0) lam[c] = 0.5 * (lo + hi);
+    if (live && half == 0 && lane == 0) lam[c] = 0.5 * (lo + hi);
 }
 
 // Twisted-factorisation eigenvectors, TW_VPB per workgroup of one wave: lane 2v runs the
@@ -675,7 +689,7 @@ void launch_tri_eigen(const double* d, const double* e, int K, int r, double* wo
                       hipStream_t st) {
     double* lam = work;
     double* info = work + r;
-    hipLaunchKernelGGL(k_tri_bisect, dim3((r + 3) / 4), dim3(256), 0, st, d, e, K, r, lam, info);
+    hipLaunchKernelGGL(k_tri_bisect, dim3((r + 1) / 2), dim3(256), 0, st, d, e, K, r, lam, info);
     if (K <= TW_LDS / 8)
         hipLaunchKernelGGL(k_tri_twisted<8>, dim3((r + 7) / 8), dim3(64), 0, st, d, e, K, r, lam,
                            info, Zr);
