@@ -262,21 +262,36 @@ struct TailScalars {
     int verdict;      // 0: keep action j; 1: tolerance stop; 2: breakdown; 3: non-finite
 };
 
-__device__ TailScalars tail_scalars(const TailArgs& ta, int j, const LoopState* ls) {
+// The step's loads (issued before anything that depends on them, so that a caller can put
+// them in flight together with its own): this lane's share of s_j^T u_j and the scalars.
+struct TailIn {
+    double fu, qjj, c_j, l2, la, tt, q00;
+};
+
+__device__ __forceinline__ TailIn tail_load(const TailArgs& ta, int j, const LoopState* ls) {
     const int lane = threadIdx.x & 63, ld = ta.imax;
-    double fu = 0.0;
-    for (int b = lane; b < ta.nfu; b += 64) fu += ta.fupart[b];
-    fu = wave_sum(fu);
-    const double* tri = ta.tri;
-    const double qjj = ta.colvec[2 * j], c_j = ta.colvec[2 * j + 1];
-    const double l2 = tri[tri_scal(ld)], la = tri[tri_scal(ld) + 1];
-    const double cjj = fu - tri[tri_scal(ld) + 2] + ta.noise_var * qjj;
+    TailIn in;
+    in.fu = 0.0;
+    for (int b = lane; b < ta.nfu; b += 64) in.fu += ta.fupart[b];
+    in.qjj = ta.colvec[2 * j];
+    in.c_j = ta.colvec[2 * j + 1];
+    in.l2 = ta.tri[tri_scal(ld)];
+    in.la = ta.tri[tri_scal(ld) + 1];
+    in.tt = ta.tri[tri_scal(ld) + 2];
+    in.q00 = j > 0 ? ls->q00 : 0.0;
+    return in;
+}
+
+__device__ TailScalars tail_finish(const TailArgs& ta, int j, const TailIn& in) {
+    const double fu = wave_sum(in.fu);
+    const double qjj = in.qjj;
+    const double cjj = fu - in.tt + ta.noise_var * qjj;
     TailScalars r{0.0, 0.0, 0.0, 0};
-    if (j > 0 && ta.resid_tol > 0.0 && qjj <= ta.resid_tol * ta.resid_tol * ls->q00) {
+    if (j > 0 && ta.resid_tol > 0.0 && qjj <= ta.resid_tol * ta.resid_tol * in.q00) {
         r.verdict = 1;
         return r;
     }
-    const double d2 = cjj - l2;
+    const double d2 = cjj - in.l2;
     const bool finite = isfinite(d2) && isfinite(cjj);
     if (!(finite && d2 > ta.pivot_tol * cjj && d2 > 0.0)) {
         r.verdict = finite ? 2 : 3;
@@ -284,8 +299,12 @@ __device__ TailScalars tail_scalars(const TailArgs& ta, int j, const LoopState* 
     }
     r.dj = sqrt(d2);
     r.inv_d = 1.0 / r.dj;
-    r.aj = (c_j - la) * r.inv_d;
+    r.aj = (in.c_j - in.la) * r.inv_d;
     return r;
+}
+
+__device__ TailScalars tail_scalars(const TailArgs& ta, int j, const LoopState* ls) {
+    return tail_finish(ta, j, tail_load(ta, j, ls));
 }
 
 // entry l <= j of row j of L^{-1} and of beta_j
@@ -710,16 +729,30 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
             mo[b][4 * k4 + 3] = x.w;
         }
     }
-    TailScalars ts{0.0, 0.0, 0.0, 0};
-    if (tail) {
-        ts = tail_scalars(ta, j, ls);
-        if (blockIdx.x == 0) tail_store(ta, ts, j, ls);
-        if (ts.verdict != 0) return;
-    }
+    // the Cholesky step's inputs and, for the residual, beta_{j-1} and row j of the
+    // triangular products, loaded with the rows above
+    TailIn tin{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double bprev[LPL], nrw[LPL];
+    if (tail) tin = tail_load(ta, j, ls);
 #pragma unroll
     for (int v = 0; v < LPL; ++v) {
         const int l = lane + 64 * v;
-        bl[v] = (RESID && l <= j) ? (float)tail_beta(ta, ts, j, l) : 0.0f;
+        const bool in = RESID && tail && l < j;
+        bprev[v] = in ? ta.beta_in[l] : 0.0;
+        nrw[v] = in ? ta.tri[tri_nrow(ta.imax) + l] : 0.0;
+    }
+    TailScalars ts{0.0, 0.0, 0.0, 0};
+    if (tail) {
+        ts = tail_finish(ta, j, tin);
+        if (blockIdx.x == 0) tail_store(ta, ts, j, ls);
+        if (ts.verdict != 0) return;
+    }
+    // beta_j = beta_{j-1} + alpha_j (row j of L^{-1}), as in tail_beta
+#pragma unroll
+    for (int v = 0; v < LPL; ++v) {
+        const int l = lane + 64 * v;
+        const double lv = l < j ? -nrw[v] * ts.inv_d : ts.inv_d;
+        bl[v] = (RESID && l <= j) ? (float)__builtin_fma(ts.aj, lv, bprev[v]) : 0.0f;
     }
     const float bj = RESID ? (float)(ts.aj * ts.inv_d) : 0.0f;
     float rho[RW];
