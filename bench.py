@@ -194,6 +194,29 @@ def rate_probe():
     print(json.dumps(out), flush=True)
 
 
+def smoother_block_product(f, fwd, cfg, peak):
+    """A second backward pass of the smoother with its block product timed: mean launch
+    duration and the algorithmic MFMA fraction (2 n^2 b summed over the launches, b = 1 +
+    the smoothed rank before the step) / the launches' time / peak."""
+    f.profile(["block_product"])
+    f.smooth_begin(fwd[-1][3], fwd[-1][4])
+    for k in range(cfg.T - 2, -1, -1):
+        mean, M, Mp, idx, rec = fwd[k]
+        f.smooth_step(mean, M, Mp, idx, rec)
+    prof = f.profile_read()
+    f.profile(False)
+    ms, launches = prof["block_product"]
+    # columns b = 1 + the smoothed factor's rank before the step: i after the first step,
+    # then growing by i per step until truncated to r
+    rank, flop = cfg.i, 0.0
+    for _ in range(launches):
+        flop += 2.0 * cfg.n * cfg.n * (1 + rank)
+        rank = min(rank + cfg.i, cfg.r)
+    return {"launches": launches, "avg_launch_us": ms * 1e3 / max(launches, 1),
+            "columns_steady": cfg.r + 1,
+            "mfma_frac_algorithmic": flop / (ms * 1e-3) / peak if ms > 0 else None}
+
+
 def next_rows(seed=0):
     """The rows built after the hot path, each timed on its own workload (not part of the
     headline):
@@ -272,13 +295,47 @@ def next_rows(seed=0):
         f.smooth_step(mean, M, Mp, idx, rec)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    bp32 = smoother_block_product(f, fwd, cfg, 157.3e12)
+    f.close()
+    del fwd
+    torch.cuda.empty_cache()
+    # the same backward pass with the BF16X3 block product (its own forward run)
+    f = CAKF(X, nu2=cfg.nu2, dist="geodesic", lengthscale=cfg.ell, signal_var=cfg.sigma_f2,
+             noise_var=cfg.noise_var, ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i,
+             max_rank=cfg.r, policy="cg", prec="bf16x3", smoother=True)
+    fwd = []
+    for idx, y in steps:
+        f.predict()
+        _, Mp = f.state()
+        rec = Record(cfg.m, cfg.i)
+        f.update(idx, y, None, rec)
+        mean, M = f.state()
+        fwd.append((mean, M, Mp, idx, rec))
+        f.truncate()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    f.smooth_begin(fwd[-1][3], fwd[-1][4])
+    for k in range(cfg.T - 2, -1, -1):
+        mean, M, Mp, idx, rec = fwd[k]
+        f.smooth_step(mean, M, Mp, idx, rec)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    bp16 = smoother_block_product(f, fwd, cfg, 2.5e15)
     f.close()
     out["smoother"] = {
         "workload": f"{cfg.name}: n={cfg.n} sphere, Matern-{cfg.nu2}/2 great-circle, m={cfg.m}, "
                     f"i={cfg.i} CG actions, r={cfg.r}, T={cfg.T}, fp32",
         "filter_ms_per_step": (t1 - t0) * 1e3 / cfg.T,
         "smoother_ms_per_step": (t2 - t1) * 1e3 / (cfg.T - 1),
-        "note": "filter steps include copying M_k and M_k^- out for the smoother"}
+        "block_product_fp32": bp32,
+        "smoother_ms_per_step_bf16x3": (t4 - t3) * 1e3 / (cfg.T - 1),
+        "block_product_bf16x3": bp16,
+        "note": "filter steps include copying M_k and M_k^- out for the smoother; the block "
+                "product K(X, X) [ws Ws] (Alg. 3) over all n points, b = r + 1 columns once "
+                "the smoothed factor is truncated; mfma_frac_algorithmic = 2 n^2 b per "
+                "launch / its mean duration / the dense MFMA peak of the mode (FP32 157.3, "
+                "BF16 2500 TFLOP/s), timed in a second backward pass with the launches "
+                "bracketed by events"}
     del fwd
     torch.cuda.empty_cache()
 
