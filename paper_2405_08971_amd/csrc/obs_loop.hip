@@ -363,11 +363,10 @@ __device__ void tail_store(const TailArgs& ta, const TailScalars& ts, int j, Loo
 constexpr int TF_LDS_N = 128;
 constexpr int TF_THREADS = 1024;
 
-// Cholesky pivots of the packed-by-rows lower triangle A (row stride la) of order ie, in
-// place (A in LDS or in global memory: one instantiation each, so that the accesses are
-// of that memory's own kind).
-template <typename Ptr>
-__device__ void tf_cholesky(Ptr A, int la, int ie, double* piv) {
+// Cholesky pivots of the lower triangle A (row stride la) of order ie, in place, by the
+// 32 x 32 thread grid.  In LDS: the thread's entries row by row (the loads' latency is
+// short).
+__device__ void tf_cholesky_lds(double* A, int la, int ie, double* piv) {
     const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
     for (int k = 0; k < ie; ++k) {
         const double dk = sqrt(fmax(A[k * la + k], 1e-300));
@@ -381,6 +380,39 @@ __device__ void tf_cholesky(Ptr A, int la, int ie, double* piv) {
             const double aik = A[i * la + k];
             for (int l = l0; l <= i; l += 32) A[i * la + l] -= aik * A[l * la + k];
         }
+        __syncthreads();
+    }
+}
+
+// In global memory (more than TF_LDS_N actions): the column's entries at the thread's
+// rows and columns first, then all its updates, so that the loads are in flight together.
+template <int QN>
+__device__ void tf_cholesky(double* A, int la, int ie, double* piv) {
+    const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
+    for (int k = 0; k < ie; ++k) {
+        const double dk = sqrt(fmax(A[k * la + k], 1e-300));
+        const double rk = 1.0 / dk;
+        if (tid == 0) piv[k] = dk;
+        // this thread's first trailing row and column (i = r, l = c modulo 32)
+        const int i0 = k + 1 + ((r - (k + 1)) & 31), l0 = k + 1 + ((c - (k + 1)) & 31);
+        for (int i = k + 1 + tid; i < ie; i += TF_THREADS) A[i * la + k] *= rk;
+        __syncthreads();
+        // the column's entries at the thread's QN rows and QN columns, then its entries
+        // (i, l), l <= i (ie <= 32 QN), all loads in flight together
+        double ci[QN], cl[QN];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int i = i0 + 32 * q, l = l0 + 32 * q;
+            ci[q] = i < ie ? A[i * la + k] : 0.0;
+            cl[q] = l < ie ? A[l * la + k] : 0.0;
+        }
+#pragma unroll
+        for (int qi = 0; qi < QN; ++qi)
+#pragma unroll
+            for (int ql = 0; ql <= qi; ++ql) {
+                const int i = i0 + 32 * qi, l = l0 + 32 * ql;
+                if (i < ie && l <= i) A[i * la + l] -= ci[qi] * cl[ql];
+            }
         __syncthreads();
     }
 }
@@ -408,12 +440,12 @@ __global__ __launch_bounds__(TF_THREADS) void k_tail_final(TailArgs ta, int j,
         for (int i = r; i < ie; i += 32)
             for (int l = c; l <= i; l += 32) Al[i * la + l] = ta.SS[(size_t)i * ld + l];
         __syncthreads();
-        tf_cholesky(Al, la, ie, piv);
+        tf_cholesky_lds(Al, la, ie, piv);
     } else {
         for (int i = r; i < ie; i += 32)
             for (int l = c; l <= i; l += 32) work[i * ld + l] = ta.SS[(size_t)i * ld + l];
         __syncthreads();
-        tf_cholesky(work, ld, ie, piv);
+        tf_cholesky<8>(work, ld, ie, piv);
     }
     double lg = 0.0;
     for (int t = tid; t < ie; t += TF_THREADS) lg += 2.0 * log(piv[t]);
