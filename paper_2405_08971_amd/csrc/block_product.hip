@@ -349,7 +349,8 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
                                                 nsplit > 1 ? qchunk : m, stride)));
         }
     } else {
-        const int ntiles = (bcols + 31) / 32;
+        const bool lone = fp32_col >= 32 && fp32_col == bcols - 1 && fp32_col % 32 == 0;
+        const int ntiles = (bcols + 31) / 32 - (lone ? 1 : 0);
         const size_t total = (size_t)mp * ntiles * 32;
         hipLaunchKernelGGL(k_split_bt, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
                            dim3(256), 0, st, B, mp, ldb, bcols, ntiles * 32,
@@ -357,7 +358,8 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
         for (int t0 = 0; t0 < ntiles; t0 += 5) {
             const int nt = std::min(5, ntiles - t0);
             // the FP32 column is summed by the launch whose tiles hold it
-            const int fc = (fp32_col >= 32 * t0 && fp32_col < std::min(32 * (t0 + nt), bcols))
+            const int fc = (fp32_col >= 32 * t0 && fp32_col < std::min(32 * (t0 + nt), bcols)) ||
+                                   (lone && t0 + nt == ntiles)
                                ? fp32_col : -1;
             if (prec == 2) {
                 CAKF_DISPATCH_KERNEL(nu2, dist,
