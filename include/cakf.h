@@ -163,7 +163,9 @@ int cakf_reset(cakf_ctx* ctx);
  * row-major with leading dimension *ld); N = n, or 2n with the Matérn-3/2 temporal
  * factor.  The pointers stay valid until the next
  * cakf_update / cakf_truncate / cakf_step / cakf_set_state / cakf_destroy.  Any output
- * pointer may be NULL. */
+ * pointer may be NULL.  The views are read-only: after a truncation the context relies on
+ * the factor's leading max_rank columns being the orthogonal columns M V_r it wrote (their
+ * Gram block is not recomputed), so a state is changed through cakf_set_state only. */
 int cakf_state(cakf_ctx* ctx, float** mean, float** factor, int* ld, int* rank);
 
 /* Copy the state out into caller-owned device buffers: mean (N) and factor (N x rank,
@@ -191,7 +193,10 @@ int cakf_update(cakf_ctx* ctx, const int32_t* idx, const float* y, int m,
  * min(max_rank, rank) eigenvectors of M^T M (FP64 Gram and FP64 eigensolver), so that
  * M M^T keeps its best rank-r approximation.  rotation (device FP64, rank x r_new,
  * row-major, nullable) receives V_r.  A factor of at most max_rank columns is left
- * unchanged. */
+ * unchanged.  The kept columns are mutually orthogonal with the kept eigenvalues as squared
+ * norms, and stay so through OU predictions (scaled by a^2) and updates (which append
+ * columns): the next truncation takes that diagonal block of M^T M as known and computes
+ * only the products that involve the appended columns. */
 int cakf_truncate(cakf_ctx* ctx, double* rotation);
 
 /* One filter step of Alg. 1: predict, update (skipped when m == 0), truncate. */

@@ -55,6 +55,12 @@ struct cakf_ctx {
     float* M[2];
     int cur;          // index of the buffer holding the factor
     int rank;
+    // the first orth columns of the factor are mutually orthogonal with squared norms
+    // orth_scale * lam[c]: the columns M V_r of the last truncation, scaled by the
+    // predictions since (0 when not known)
+    int orth;
+    double orth_scale;
+    double* lam;
     // observation space workspace
     float4* Xs;
     float4* Xo;
@@ -203,7 +209,7 @@ static void free_all(cakf_ctx* c) {
                     c->part, c->cpart, c->colvec, c->fupart, c->tri, c->ctr, c->ttpart, c->beta2, c->SS, c->SSwork, c->mpart, c->Linv,
                     c->LinvT, c->L, c->LSinv, c->LSinvT,
                     c->alpha, c->beta, c->ls, c->diag, c->B, c->Q, c->Bth, c->Btl, c->G, c->gwork, c->eigval,
-                    c->offdiag, c->info, c->Vr, c->tdV, c->tdtau, c->tdp, c->tdrow, c->tdctr,
+                    c->lam, c->offdiag, c->info, c->Vr, c->tdV, c->tdtau, c->tdp, c->tdrow, c->tdctr,
                     c->tdabort, c->blas_ws, c->Xp, c->sm_ws, c->sm_W[0],
                     c->sm_W[1], c->sm_B, c->sm_Y, c->sm_Z, c->sm_Q, c->sm_Gr, c->sm_R,
                     c->sm_WR, c->sm_Bth, c->sm_Btl, c->gMb[0], c->gMb[1], c->gmb, c->gYb,
@@ -386,6 +392,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     rc |= dalloc(&c->G, (size_t)c->Kmax * c->Kmax);
     rc |= dalloc(&c->gwork, c->gram_work_elems);
     rc |= dalloc(&c->eigval, c->Kmax);
+    rc |= dalloc(&c->lam, std::max(c->r, 1));
     rc |= dalloc(&c->offdiag, c->Kmax);
     rc |= dalloc(&c->info, 1);
     rc |= dalloc(&c->Vr, (size_t)c->Kmax * c->r);
@@ -536,6 +543,8 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
     }
     c->cur = 0;
     c->rank = 0;
+    c->orth = 0;
+    c->orth_scale = 1.0;
     *out = c;
     return CAKF_OK;
 }
@@ -554,6 +563,7 @@ extern "C" int cakf_reset(cakf_ctx* c) {
     HIP_TRY(hipMemsetAsync(c->mean, 0, (size_t)c->N * sizeof(float), c->stream));
     HIP_TRY(hipMemsetAsync(c->diag, 0, sizeof(Diag), c->stream));
     c->rank = 0;
+    c->orth = 0;
     return CAKF_OK;
 }
 
@@ -584,6 +594,7 @@ extern "C" int cakf_set_state(cakf_ctx* c, const float* mean, const float* facto
                            c->stream));
     if (rank > 0) launch_copy_rows(factor, ld, c->M[c->cur], c->ldM, c->N, rank, c->stream);
     c->rank = rank;
+    c->orth = 0;
     return CAKF_OK;
 }
 
@@ -596,8 +607,10 @@ extern "C" int cakf_predict(cakf_ctx* c) {
         const float t[4] = {(float)(ad * (1.0 + sd)), (float)(ad * sd), (float)(-ad * sd),
                             (float)(ad * (1.0 - sd))};
         launch_predict_pairs(c->mean, c->M[c->cur], c->n, c->ldM, c->rank, t, c->stream);
+        c->orth = 0;        // the transition mixes the value and derivative rows
     } else if (a != 1.0f) {
         launch_scale_state(c->mean, c->M[c->cur], c->n, c->ldM, c->rank, a, c->stream);
+        c->orth_scale *= (double)a * (double)a;
     }
     return CAKF_OK;
 }
@@ -840,13 +853,17 @@ static TruncWork context_work(cakf_ctx* c) {
 }
 
 // Replace the rows x K factor M (row-major, ld) by M V_r in Mout (ld ldo), V_r the leading
-// r eigenvectors of M^T M (FP64 Gram, FP64 symmetric eigensolver, FP32 rotation).
+// r eigenvectors of M^T M (FP64 Gram, FP64 symmetric eigensolver, FP32 rotation).  With
+// lam, the first orth columns of M are known to be orthogonal with squared norms
+// orth_scale * lam (their Gram block is not computed), and lam receives the r kept
+// eigenvalues in descending order, the squared norms of the columns of Mout.
 static int truncate_factor(cakf_ctx* c, const TruncWork& w, const float* M, int rows, int ld,
-                           int K, int r, float* Mout, int ldo, double* rotation) {
+                           int K, int r, float* Mout, int ldo, double* rotation, int orth = 0,
+                           double orth_scale = 1.0, double* lam = nullptr) {
     hipStream_t st = c->stream;
     {
         PhaseTimer t(c, CAKF_PHASE_GRAM);
-        launch_gram64(M, rows, ld, K, w.G, w.gwork, w.gwork_elems, st);
+        launch_gram64(M, rows, ld, K, w.G, w.gwork, w.gwork_elems, st, orth, lam, orth_scale);
     }
     bool picked = false;
     {
@@ -881,14 +898,17 @@ static int truncate_factor(cakf_ctx* c, const TruncWork& w, const float* M, int 
                 BLAS_TRY(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none,
                                        r, K, r, &one, E2, r, Zr, r, &zero, Zx, r));
                 launch_backtransform(Zx, r, 1, w.tdV, w.tdtau, K, r, w.Vr, rotation, st);
+                if (lam) launch_store_lam(E2 + (size_t)r * r, K, r, 0, lam, st);
                 picked = true;
             } else {
                 (void)hipGetLastError();
             }
         }
-        if (!picked)
+        if (!picked) {
             BLAS_TRY(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, K,
                                       w.G, K, w.eigval, w.offdiag, w.info));
+            if (lam) launch_store_lam(w.eigval, K, r, 1, lam, st);
+        }
     }
     {
         PhaseTimer t(c, CAKF_PHASE_ROTATE);
@@ -907,10 +927,13 @@ extern "C" int cakf_truncate(cakf_ctx* c, double* rotation) {
     const int K = c->rank;
     if (K <= c->r) return CAKF_OK;
     int rc = truncate_factor(c, context_work(c), c->M[c->cur], c->N, c->ldM, K, c->r,
-                             c->M[1 - c->cur], c->ldM, rotation);
+                             c->M[1 - c->cur], c->ldM, rotation, c->orth, c->orth_scale,
+                             c->lam);
     if (rc) return rc;
     c->cur = 1 - c->cur;
     c->rank = c->r;
+    c->orth = c->r;
+    c->orth_scale = 1.0;
     return hipGetLastError() == hipSuccess ? CAKF_OK : CAKF_E_HIP;
 }
 

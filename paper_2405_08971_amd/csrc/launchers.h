@@ -180,8 +180,14 @@ void launch_gather_points(const float4* Xs, int n, const int32_t* idx, int m, in
                           float4* Xo, hipStream_t st);
 
 // ---- truncate.hip
+// orth > 0 with lam: the leading orth x orth block of the Gram is diag(scale * lam) (known
+// orthogonal columns); its full 64 x 64 tiles are not computed
 void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* work,
-                   size_t work_elems, hipStream_t st);
+                   size_t work_elems, hipStream_t st, int orth = 0,
+                   const double* lam = nullptr, double scale = 1.0);
+// lam[c] (c < r) = src[K - 1 - c] if ascending, else src[c]
+void launch_store_lam(const double* src, int K, int r, int ascending, double* lam,
+                      hipStream_t st);
 void launch_pick_rotation(const double* E, int K, int r, float* Vr, double* rot_out,
                           hipStream_t st);
 

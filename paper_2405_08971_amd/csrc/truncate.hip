@@ -22,11 +22,14 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // and B[l / 16][l % 16] = M[row l / 16, column l % 16 of the d sub-block], widened to
 // FP64, and holds D[l / 16 + 4 i][l % 16] in register i (rows interleaved by 4, unlike
 // the FP32 16 x 16 x 4 form).
+//
+// Tiles are enumerated row block by row block (tile = tc (tc + 1) / 2 + td); the first
+// tile_off of them (the leading columns whose Gram is known, below) are not launched.
 __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ M, int n,
-                                                      int ldM, int K, int nsplit,
+                                                      int ldM, int K, int nsplit, int tile_off,
                                                       double* __restrict__ work) {
     __shared__ float As[GROWS][GLD], Bs[GROWS][GLD];
-    const int tile = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+    const int tile = blockIdx.x / nsplit + tile_off, split = blockIdx.x % nsplit;
     int tc = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
     while ((tc + 1) * (tc + 2) / 2 <= tile) ++tc;
     while (tc * (tc + 1) / 2 > tile) --tc;
@@ -115,13 +118,19 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
             }
 }
 
-// G = sum over splits (fixed order), lower tiles mirrored to the full symmetric matrix.
-__global__ void k_gram_reduce(const double* __restrict__ work, int K, int nsplit,
+// G = sum over splits (fixed order), lower tiles mirrored to the full symmetric matrix;
+// the leading kk x kk block (kk > 0) is the diagonal matrix scale * lam.
+__global__ void k_gram_reduce(const double* __restrict__ work, int K, int nsplit, int kk,
+                              const double* __restrict__ lam, double scale,
                               double* __restrict__ G) {
     const size_t total = (size_t)K * K;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(e / K), d = (int)(e % K);
+        if (c < kk && d < kk) {
+            G[e] = c == d ? scale * lam[c] : 0.0;
+            continue;
+        }
         if (c / GT < d / GT) continue;                  // upper tiles: mirrored below
         double s = 0.0;
         for (int sp = 0; sp < nsplit; ++sp) s += work[(size_t)sp * total + e];
@@ -131,19 +140,42 @@ __global__ void k_gram_reduce(const double* __restrict__ work, int K, int nsplit
 }
 
 // M must be 16-byte aligned with ldM a multiple of 4 (true of every factor buffer: device
-// allocations with leading dimensions rounded up to 4), and K <= ldM.
+// allocations with leading dimensions rounded up to 4), and K <= ldM.  With lam, the first
+// orth columns of M are mutually orthogonal with squared norms scale * lam[c] (the columns
+// of a truncated factor, M V_r, scaled by the predictions since): the Gram tiles inside
+// that block are not computed but taken as that diagonal.
 void launch_gram64(const float* M, int n, int ldM, int K, double* G, double* work,
-                   size_t work_elems, hipStream_t st) {
+                   size_t work_elems, hipStream_t st, int orth, const double* lam,
+                   double scale) {
     const int nt = (K + GT - 1) / GT;
-    const int tiles = nt * (nt + 1) / 2;
-    int nsplit = std::max(1, (2048 + tiles - 1) / tiles);
-    nsplit = std::min(nsplit, std::max(1, n / 256));
-    while (nsplit > 1 && (size_t)nsplit * K * K > work_elems) --nsplit;
-    hipLaunchKernelGGL(k_gram_partial, dim3(tiles * nsplit), dim3(256), 0, st, M, n, ldM, K,
-                       nsplit, work);
+    const int ot = lam ? std::min(std::min(orth, K) / GT, nt) : 0;
+    const int tile_off = ot * (ot + 1) / 2;
+    const int tiles = nt * (nt + 1) / 2 - tile_off;
+    int nsplit = 1;
+    if (tiles > 0) {
+        nsplit = std::max(1, (2048 + tiles - 1) / tiles);
+        nsplit = std::min(nsplit, std::max(1, n / 256));
+        while (nsplit > 1 && (size_t)nsplit * K * K > work_elems) --nsplit;
+        hipLaunchKernelGGL(k_gram_partial, dim3(tiles * nsplit), dim3(256), 0, st, M, n, ldM,
+                           K, nsplit, tile_off, work);
+    }
     const size_t total = (size_t)K * K;
     const int blocks = (int)std::min<size_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, st, work, K, nsplit, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, st, work, K, nsplit, ot * GT,
+                       lam, scale, G);
+}
+
+// lam[c] (c < r) = src[K - 1 - c] (ascending src, the library solver's order) or src[c]
+__global__ void k_store_lam(const double* __restrict__ src, int K, int r, int ascending,
+                            double* __restrict__ lam) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < r) lam[c] = ascending ? src[K - 1 - c] : src[c];
+}
+
+void launch_store_lam(const double* src, int K, int r, int ascending, double* lam,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_store_lam, dim3((r + 255) / 256), dim3(256), 0, st, src, K, r,
+                       ascending, lam);
 }
 
 // The eigensolver returns eigenvalues in ascending order with eigenvectors as columns

@@ -65,6 +65,20 @@ def test_more_than_160_block_columns(prec, tol):
     _check(compare(cfg, model, recs, gpu, probes), tol)
 
 
+def test_truncation_with_the_kept_columns_gram_block_known():
+    """r = 128 (two full 64-column Gram tiles), i = 64: after the first truncation (step 3)
+    the kept columns are orthogonal with the kept eigenvalues as squared norms, so the
+    truncations of steps 4 and 6 take that block of M^T M as diag(a^2 lam) (a^4 across the
+    missing step 5) and compute only the products with the appended columns.  The oracle
+    forms every Gram entry in FP64."""
+    cfg = small_config("orth", n=2000, m=500, i=64, r=128, T=6)
+    X, steps, actions = inputs(cfg, seed=21, missing_steps=(5,))
+    model, recs = oracle_run(cfg, X, steps, actions, "given")
+    probes = np.random.default_rng(5).standard_normal((cfg.n, 3))
+    gpu = gpu_run(cfg, X, steps, actions, "given", "fp32", probes=probes)
+    _check(compare(cfg, model, recs, gpu, probes), FP32_TOL)
+
+
 def test_cg_fp32_matches_oracle_end_to_end():
     cfg = small_config("cg", n=700, m=220, i=6, r=15, T=5)
     X, steps, _ = inputs(cfg, seed=2, policy="cg")
