@@ -130,7 +130,7 @@ typedef struct {
     int sample_paths;       /* largest number of paths per sampler call, 0..256
                                (0: no sampler workspace)                              */
     int gradient;           /* nonzero: also allocate the workspace of
-                               cakf_loglik_grad (needs max_actions <= 159)           */
+                               cakf_loglik_grad (needs max_actions <= 256)           */
     void* stream;           /* hipStream_t for all work; NULL = the null stream      */
 } cakf_config;
 
@@ -401,7 +401,7 @@ typedef struct {
  * derivative of the filter as it was run; the paper leaves evidence maximisation to future
  * work, Sec. 8).  Reverse sweep over the steps of Alg. 1 and Alg. 2: kernel tiles are
  * recomputed, nothing of size n x m is stored.  Needs cfg.gradient != 0, the context's
- * max_actions <= 159 and distinct indices within each step; dt < 0 is CAKF_E_ARG.
+ * max_actions <= 256 and distinct indices within each step; dt < 0 is CAKF_E_ARG.
  * grad: host, 4 doubles.  Synchronises the stream. */
 int cakf_loglik_grad(cakf_ctx* ctx, int T, const cakf_tape_step* tape, double dt,
                      double* grad);

@@ -64,6 +64,7 @@ __device__ __forceinline__ float pair_dist(const float4 ap, const float4 b) {
 // (zero padded to W = 32 CT in LDS); bk = b rounded up to even is the MFMA depth of
 // Yp Bq^T.  Four waves take 32 rows each of a staged chunk of AT_CHUNK rows.
 constexpr int AT_CHUNK = 128;
+constexpr int AT_MAXCOL = 160;   // columns per launch (LDS: 128 + 32 staged rows of them)
 
 template <int NU2, int DIST, bool BBAR, int CT>
 __global__ __launch_bounds__(256) void k_adj_tiles(const float4* __restrict__ Xp, int np_,
@@ -214,10 +215,11 @@ void adj_tiles_geometry(int np_, int mq, int* gx, int* gy, int* rps) {
     *gy = (np_ + *rps - 1) / *rps;
 }
 
-int launch_adj_tiles(int nu2, int dist, bool bbar, const float4* Xp, int np_, const float* Yp,
-                     int ldy, const float4* Xq, int mq, const float* Bq, int ldb, int b,
-                     float* bpart, int ldbp, size_t slice_stride, double* spart,
-                     int* nblocks, hipStream_t st) {
+// One launch over at most AT_MAXCOL columns.
+static int launch_adj_block(int nu2, int dist, bool bbar, const float4* Xp, int np_,
+                            const float* Yp, int ldy, const float4* Xq, int mq, const float* Bq,
+                            int ldb, int b, float* bpart, int ldbp, size_t slice_stride,
+                            double* spart, int* nblocks, hipStream_t st) {
     const int ct = (b + 31) / 32;
     if (ct < 1 || ct > 5 || mq < 1 || np_ < 1) return -1;
     const int bk = (b + 1) & ~1;
@@ -242,6 +244,27 @@ int launch_adj_tiles(int nu2, int dist, bool bbar, const float4* Xp, int np_, co
     }
 #undef CAKF_ADJ_LAUNCH
     return rc ? rc : (int)grid.y;
+}
+
+// Both sums are linear in the columns: more than AT_MAXCOL columns are taken in blocks of
+// AT_MAXCOL, each launch writing its own columns of bpart and its own run of per-block
+// partials after the previous launch's (spart then holds *nblocks partials in all).
+int launch_adj_tiles(int nu2, int dist, bool bbar, const float4* Xp, int np_, const float* Yp,
+                     int ldy, const float4* Xq, int mq, const float* Bq, int ldb, int b,
+                     float* bpart, int ldbp, size_t slice_stride, double* spart,
+                     int* nblocks, hipStream_t st) {
+    if (b < 1) return -1;
+    int total = 0, ns = -1;
+    for (int c0 = 0; c0 < b; c0 += AT_MAXCOL) {
+        int nb = 0;
+        ns = launch_adj_block(nu2, dist, bbar, Xp, np_, Yp + c0, ldy, Xq, mq, Bq + c0, ldb,
+                              std::min(AT_MAXCOL, b - c0), bbar ? bpart + c0 : bpart, ldbp,
+                              slice_stride, spart + 2 * (size_t)total, &nb, st);
+        if (ns < 0) return ns;
+        total += nb;
+    }
+    *nblocks = total;
+    return ns;
 }
 
 // Bbar[q, c] = scale * sum over the slices of bpart (fixed order), c < b; zero for rows

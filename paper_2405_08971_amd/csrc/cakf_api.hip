@@ -257,7 +257,8 @@ static int validate(const cakf_config* c) {
         return CAKF_E_ARG;
     if (c->resid_tol < 0 || c->pivot_tol < 0) return CAKF_E_ARG;
     if (c->smoother && (size_t)c->n * (c->max_rank + 1) > ((size_t)1 << 31)) return CAKF_E_ARG;
-    if (c->gradient && c->max_actions > 159) return CAKF_E_ARG;
+    // the reverse sweep's FP64 Cholesky adjoint keeps per-action vectors of 256 in LDS
+    if (c->gradient && c->max_actions > 256) return CAKF_E_ARG;
     if (c->sample_paths < 0 || c->sample_paths > 256) return CAKF_E_ARG;
     if (c->temporal != CAKF_TEMPORAL_OU && c->temporal != CAKF_TEMPORAL_MATERN32)
         return CAKF_E_ARG;
@@ -451,7 +452,7 @@ extern "C" int cakf_create(const cakf_config* cfg, cakf_ctx** out) {
         // slices x (m rounded to 32) <= 2048 x 32 + mpmax rows of partials
         c->gbpart_elems = ((size_t)2048 * 32 + c->mpmax) * c->bp;
         rc |= dalloc(&c->gbpart, c->gbpart_elems);
-        c->gspart_blocks = 2048 + c->mpmax / 32 + 1;
+        c->gspart_blocks = adj_tiles_launches(I1) * (2048 + c->mpmax / 32 + 1);
         rc |= dalloc(&c->gspart, (size_t)2 * c->gspart_blocks);
         rc |= dalloc(&c->gQb, (size_t)c->r * c->bp);
         rc |= dalloc(&c->gMob, (size_t)c->mpmax * c->ldmo);
@@ -1000,8 +1001,9 @@ extern "C" int cakf_loglik_grad(cakf_ctx* c, int T, const cakf_tape_step* tape, 
                 int gx, gy, rps, gx2, gy2, rps2;
                 adj_tiles_geometry(n, m, &gx, &gy, &rps);
                 adj_tiles_geometry(m, m, &gx2, &gy2, &rps2);
-                if ((size_t)gy * mp * bp > c->gbpart_elems || gx * gy > c->gspart_blocks ||
-                    gx2 * gy2 > c->gspart_blocks)
+                if ((size_t)gy * mp * bp > c->gbpart_elems ||
+                    gx * gy * adj_tiles_launches(imax + 1) > c->gspart_blocks ||
+                    gx2 * gy2 * adj_tiles_launches(imax) > c->gspart_blocks)
                     return CAKF_E_ARG;
             }
             int nblk = 0;

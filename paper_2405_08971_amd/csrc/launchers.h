@@ -235,6 +235,9 @@ hipError_t probe_rates(double* out);
 // ---- adjoint.hip
 // launch shape of k_adj_tiles: gx blocks of 32 q-points x gy slices of rps p-points
 void adj_tiles_geometry(int np_, int mq, int* gx, int* gy, int* rps);
+// b columns in launches of at most 160 (adj_tiles_launches(b) of them); *nblocks = the
+// per-block partials written into spart in all; returns the slice count gy or < 0
+constexpr int adj_tiles_launches(int b) { return (b + 159) / 160; }
 int launch_adj_tiles(int nu2, int dist, bool bbar, const float4* Xp, int np_, const float* Yp,
                      int ldy, const float4* Xq, int mq, const float* Bq, int ldb, int b,
                      float* bpart, int ldbp, size_t slice_stride, double* spart,

@@ -23,20 +23,22 @@ pytestmark = pytest.mark.gpu
 GRAD_TOL = 1e-4
 
 
-def _run(cfg, seed, missing=(), prec="fp32"):
+def _run(cfg, seed, missing=(), prec="fp32", policy="cg"):
     import torch
     from paper_2405_08971_amd.autograd import FilterLogLik
 
-    X, steps, _ = inputs(cfg, seed=seed, missing_steps=missing, policy="cg")
+    X, steps, actions = inputs(cfg, seed=seed, missing_steps=missing, policy=policy)
     dt = 1.0
     theta0 = (cfg.ell, cfg.ell_t, cfg.sigma_f2, cfg.noise_var)
     dev_steps = [None if s is None else (torch.from_numpy(s[0]).cuda(),
                                          torch.from_numpy(s[1]).cuda()) for s in steps]
+    dev_acts = None if policy == "cg" else [None if a is None else torch.from_numpy(a).cuda()
+                                            for a in actions]
     theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
     opts = dict(nu2=cfg.nu2, dist="geodesic" if cfg.dist == 1 else "euclid", dt=dt,
-                max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy="cg",
+                max_obs=cfg.m, max_actions=cfg.i, max_rank=cfg.r, policy=policy,
                 pivot_tol=1e-10, prec=prec)
-    ll = FilterLogLik.apply(theta, torch.from_numpy(X).cuda(), dev_steps, None, opts)
+    ll = FilterLogLik.apply(theta, torch.from_numpy(X).cuda(), dev_steps, dev_acts, opts)
     # the frozen actions and rotations, read back before backward releases the tape
     recs = []
     for k, keep in enumerate(FilterLogLik_last_tape(ll)):
@@ -84,6 +86,15 @@ def test_gradient_matches_fd_of_the_fp64_replay():
     fd = fd_gradient(base, dt, theta0, ost, recs, cfg.r)
     np.testing.assert_allclose(g_tan, fd, rtol=1e-6, atol=1e-8)
     _check(g, fd, GRAD_TOL)
+
+
+def test_gradient_with_more_than_160_action_columns():
+    """i = 200 given actions: the kernel-term sweeps of the reverse pass take the b = 201
+    columns of [W w] (and the 200 of S) in two column blocks (160 + 41)."""
+    cfg = small_config("gwide", n=900, m=420, i=200, r=40, T=3)
+    value_gpu, g, value, g_tan, _ = _run(cfg, seed=33, policy="given")
+    assert abs(value_gpu - value) <= 1e-5 * abs(value), (value_gpu, value)
+    _check(g, g_tan, GRAD_TOL)
 
 
 def test_gradient_on_the_sphere_geodesic():
