@@ -43,6 +43,7 @@ SAMPLE_STEPS = 20          # steps of the path-sampler timing
 SYM_STRIDE = 16            # timed steps: every 16th action-loop matvec launch is timed
 LARGE_WARMUP = 5      # steps before the timed ones on the largest workload
 LARGE_STEPS = 3
+LARGE_SG_STEPS = 6     # smoother and derivative steps on the largest workload
 GRAD_WARMUP_STEPS = 6      # untimed derivative pass before the timed one (truncation included)
 
 
@@ -232,7 +233,9 @@ def next_rows(seed=0):
       * the filter on the largest workload (n = 262144, Matern-3/2, m = 32768 of the 90%
         of locations ever observed, i = 256 CG actions, r = 1024, BF16X3 block product):
         steps/s over LARGE_STEPS steps after LARGE_WARMUP steps (the warm-up grows the factor
-        to 1280 columns, so every timed step truncates 1280 -> 1024), with its phases."""
+        to 1280 columns, so every timed step truncates 1280 -> 1024), with its phases;
+      * the smoother and the derivative on the same workload over its first LARGE_SG_STEPS
+        steps (large_smoother_and_gradient)."""
     import torch
     from paper_2405_08971_amd.autograd import loglik
     from paper_2405_08971_amd.filter import CAKF, Record
@@ -409,9 +412,79 @@ def next_rows(seed=0):
         "ms_per_step": r["elapsed"] / LARGE_STEPS * 1e3,
         "phases_ms_per_step": r["phases"], "dropped_actions": r["dropped"],
         "nonfinite": r["nonfinite"]}
-    del r, inputs, X
+    del r, inputs
+    torch.cuda.empty_cache()
+    out.update(large_smoother_and_gradient(cfg, wl, X))
+    del X
     torch.cuda.empty_cache()
     return out
+
+
+def large_smoother_and_gradient(cfg, wl, X):
+    """The smoother (Alg. 3) and the log-likelihood derivative on the largest workload over
+    its first LARGE_SG_STEPS steps (the factor grows by 256 columns a step and is truncated
+    1280 -> 1024 from step 5 on; BF16X3 block products): the filter with its states copied
+    out for the smoother, the backward pass, then the differentiable forward pass with its
+    tape and the reverse sweep."""
+    import torch
+    from paper_2405_08971_amd.autograd import loglik
+    from paper_2405_08971_amd.filter import CAKF, Record
+
+    T = LARGE_SG_STEPS
+    steps = device_inputs(wl, range(1, T + 1))
+    f = CAKF(X, nu2=cfg.nu2, dist="euclid", lengthscale=cfg.ell, signal_var=cfg.sigma_f2,
+             noise_var=cfg.noise_var, ou_coeff=cfg.a, max_obs=cfg.m, max_actions=cfg.i,
+             max_rank=cfg.r, policy="cg", prec="bf16x3", smoother=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd = []
+    for idx, y in steps:
+        f.predict()
+        _, Mp = f.state()
+        rec = Record(cfg.m, cfg.i)
+        f.update(idx, y, None, rec)
+        mean, M = f.state()
+        fwd.append((mean, M, Mp, idx, rec))
+        f.truncate()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    f.smooth_begin(fwd[-1][3], fwd[-1][4])
+    for k in range(T - 2, -1, -1):
+        mean, M, Mp, idx, rec = fwd[k]
+        f.smooth_step(mean, M, Mp, idx, rec)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f.close()
+    del fwd
+    torch.cuda.empty_cache()
+    theta = torch.tensor([cfg.ell, cfg.ell_t, cfg.sigma_f2, cfg.noise_var], dtype=torch.float64,
+                         requires_grad=True)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ll = loglik(theta, X, steps, nu2=cfg.nu2, dt=cfg.dt, max_obs=cfg.m, max_actions=cfg.i,
+                max_rank=cfg.r, prec="bf16x3")
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    ll.backward()
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    wname = (f"{cfg.name}: n={cfg.n} sphere, Matern-{cfg.nu2}/2 chordal, m={cfg.m}, i={cfg.i} "
+             f"CG actions, r={cfg.r}, T={T} (truncating from step 5), bf16x3 products")
+    res = {
+        "large_smoother": {
+            "workload": wname,
+            "filter_ms_per_step": (t1 - t0) * 1e3 / T,
+            "smoother_ms_per_step": (t2 - t1) * 1e3 / (T - 1),
+            "note": "filter steps include copying M_k and M_k^- out for the smoother; the "
+                    "smoothed rank grows by i per backward step up to r"},
+        "large_loglik_grad": {
+            "workload": wname,
+            "forward_ms_per_step": (t4 - t3) * 1e3 / T,
+            "backward_ms_per_step": (t5 - t4) * 1e3 / T,
+            "loglik": float(ll.item()),
+            "grad_ell_ellt_sigmaf2_noise": [float(g) for g in theta.grad.tolist()]}}
+    del ll, steps
+    return res
 
 
 def err_fields(x, ref):
