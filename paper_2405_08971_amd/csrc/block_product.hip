@@ -39,13 +39,16 @@ __host__ __device__ __forceinline__ int md_perm(int q) {
 }
 constexpr int MF_KC = 64;        // observations per LDS chunk (4 MFMA k-steps)
 constexpr int MF_ROWS = 128;     // state rows per workgroup (4 waves x 32)
+constexpr int MF_MAXNT = 8;      // tiles of a single launch (B parts in LDS: 2 x 37 KB at 8)
+constexpr int MF_SPLITNT = 5;    // tiles per launch when they need more than one launch
 
 template <int NU2, int DIST, int NT, bool X3>
 __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ Xs, int n,
                                                     const float4* __restrict__ Xo, int mp,
                                                     const __bf16* __restrict__ Bth,
                                                     const __bf16* __restrict__ Btl, int ldbt,
-                                                    int tile0, int ncols, float sigma_f2,
+                                                    int tile0, int ncols, int coff,
+                                                    float sigma_f2,
                                                     float* __restrict__ out, int ldo,
                                                     int qchunk, size_t part_stride,
                                                     const float* __restrict__ Bf, int ldbf,
@@ -147,11 +150,12 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
     }
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
-        const int col = (tile0 + c) * 32 + rl;
+        // MFMA column cm (of ncols) is column coff + cm of out
+        const int cm = (tile0 + c) * 32 + rl, col = coff + cm;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int row = row0 + 8 * (i / 4) + 4 * half + (i % 4);
-            if (row < n && col < ncols && col != fcol)
+            if (row < n && cm < ncols && col != fcol)
                 out[(size_t)row * ldo + col] = sigma_f2 * acc[c][i];
         }
     }
@@ -167,20 +171,24 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
 template <int NU2, int DIST, bool X3>
 static void launch_mfma_tiles(int nt, int tile0, const float4* Xs, int n, const float4* Xo,
                               int mp, const __bf16* Bth, const __bf16* Btl, int ldbt,
-                              int ncols, float sigma_f2, float* out, int ldo, int nsplit,
+                              int ncols, int coff, float sigma_f2, float* out, int ldo,
+                              int nsplit,
                               int qchunk, size_t part_stride, const float* Bf, int ldbf,
                               int fcol, hipStream_t st) {
     const dim3 grid((n + MF_ROWS - 1) / MF_ROWS, nsplit), block(256);
 #define CAKF_MF(NTV)                                                                       \
     hipLaunchKernelGGL((k_block_mfma<NU2, DIST, NTV, X3>), grid, block, 0, st, Xs, n, Xo, mp, \
-                       Bth, Btl, ldbt, tile0, ncols, sigma_f2, out, ldo, qchunk, part_stride,  \
-                       Bf, ldbf, fcol)
+                       Bth, Btl, ldbt, tile0, ncols, coff, sigma_f2, out, ldo, qchunk,        \
+                       part_stride, Bf, ldbf, fcol)
     switch (nt) {
         case 1: CAKF_MF(1); break;
         case 2: CAKF_MF(2); break;
         case 3: CAKF_MF(3); break;
         case 4: CAKF_MF(4); break;
-        default: CAKF_MF(5); break;
+        case 5: CAKF_MF(5); break;
+        case 6: CAKF_MF(6); break;
+        case 7: CAKF_MF(7); break;
+        default: CAKF_MF(8); break;
     }
 #undef CAKF_MF
 }
@@ -349,29 +357,43 @@ void launch_block_product(int nu2, int dist, int prec, const float4* Xs, int n,
                                                 nsplit > 1 ? qchunk : m, stride)));
         }
     } else {
-        const bool lone = fp32_col >= 32 && fp32_col == bcols - 1 && fp32_col % 32 == 0;
-        const int ntiles = (bcols + 31) / 32 - (lone ? 1 : 0);
+        // the FP32 column, when it is the first or the last one, is left out of the MFMA
+        // columns altogether (no tile carries it as a padded or discarded column): the first
+        // launch sums it on the VALU from the same kernel entries
+        int coff = 0, mcols = bcols;
+        if (fp32_col >= 0 && bcols >= 2 && (fp32_col == 0 || fp32_col == bcols - 1)) {
+            mcols = bcols - 1;
+            coff = fp32_col == 0 ? 1 : 0;
+        }
+        const int ntiles = (mcols + 31) / 32;
         const size_t total = (size_t)mp * ntiles * 32;
         hipLaunchKernelGGL(k_split_bt, dim3((int)std::min<size_t>((total + 255) / 256, 8192)),
-                           dim3(256), 0, st, B, mp, ldb, bcols, ntiles * 32,
+                           dim3(256), 0, st, B + coff, mp, ldb, mcols, ntiles * 32,
                            (dist == DIST_EUCLID && nu2 != 1) ? 1 : 0, Bth, Btl);
-        for (int t0 = 0; t0 < ntiles; t0 += 5) {
-            const int nt = std::min(5, ntiles - t0);
-            // the FP32 column is summed by the launch whose tiles hold it
-            const int fc = (fp32_col >= 32 * t0 && fp32_col < std::min(32 * (t0 + nt), bcols)) ||
-                                   (lone && t0 + nt == ntiles)
+        // up to MF_MAXNT tiles in one launch (the kernel entries evaluated once); more in
+        // launches of at most MF_SPLITNT tiles, as even as possible (measured: 8-tile
+        // launches at two workgroups per CU beat two launches over the same 8 tiles, but
+        // lose to 5-tile launches at three per CU once several launches are needed anyway)
+        const int nl = ntiles <= MF_MAXNT ? 1 : (ntiles + MF_SPLITNT - 1) / MF_SPLITNT;
+        for (int l = 0, t0 = 0; l < nl; ++l) {
+            const int nt = (ntiles - t0) / (nl - l) + ((ntiles - t0) % (nl - l) != 0 ? 1 : 0);
+            // the FP32 column: the first launch when it is outside the MFMA columns, else
+            // the launch whose tiles hold it
+            const int fc = mcols < bcols ? (t0 == 0 ? fp32_col : -1)
+                           : (fp32_col >= 32 * t0 && fp32_col < std::min(32 * (t0 + nt), bcols))
                                ? fp32_col : -1;
             if (prec == 2) {
                 CAKF_DISPATCH_KERNEL(nu2, dist,
                     (launch_mfma_tiles<NU2, DIST, true>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp,
-                                                        bcols, sigma_f2, dst, ldd, nsplit,
+                                                        mcols, coff, sigma_f2, dst, ldd, nsplit,
                                                         qchunk, stride, B, ldb, fc, st)));
             } else {
                 CAKF_DISPATCH_KERNEL(nu2, dist,
                     (launch_mfma_tiles<NU2, DIST, false>(nt, t0, Xs, n, Xo, mp, Bth, Btl, mp,
-                                                         bcols, sigma_f2, dst, ldd, nsplit,
+                                                         mcols, coff, sigma_f2, dst, ldd, nsplit,
                                                          qchunk, stride, B, ldb, fc, st)));
             }
+            t0 += nt;
         }
     }
     if (nsplit > 1) {
