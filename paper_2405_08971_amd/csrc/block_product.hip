@@ -69,8 +69,9 @@ __global__ __launch_bounds__(256) void k_block_mfma(const float4* __restrict__ X
     for (int c = 0; c < NT; ++c)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[c][i] = 0.0f;
-    // column fcol (>= 0) is also summed in FP32 from the FP32 kernel entries, one chunk at a
-    // time, the chunk sums added in FP64; it replaces that column's MFMA result
+    // column fcol (>= 0) of out is summed in FP32 from the FP32 kernel entries, one chunk at
+    // a time, the chunk sums added in FP64 (when it is also one of the MFMA columns, it
+    // replaces that column's MFMA result)
     const bool fp = fcol >= 0;
     double fsum = 0.0;
     // observation range of this split (qchunk a multiple of MF_KC)
