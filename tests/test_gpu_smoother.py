@@ -41,6 +41,22 @@ def test_smoother_bf16x3_and_cg_policy():
         assert em <= 1e-4 and ev <= 1e-4, (k, em, ev)
 
 
+def test_smoother_bf16x3_more_than_8_column_tiles():
+    """Given actions with r = 300: the smoothed factor reaches the b = r + 1 = 301 columns of
+    [ws Ws], whose 300 BF16X3 columns (ws, column 0, is summed in FP32) take two launches of
+    five 32-column tiles; the truncating steps take the Gram of their kept block as known."""
+    cfg = small_config("sm_wide", n=1200, m=330, i=110, r=300, T=5)
+    X, steps, actions = inputs(cfg, seed=24)
+    model, recs = oracle_run(cfg, X, steps, actions, "given")
+    sm = run_smoother(model, recs, cfg.r)
+    gpu = gpu_run_smoother(cfg, X, steps, actions, "given", "bf16x3")
+    for k in range(cfg.T):
+        em = rel_mean_err(gpu[k][0], sm[k].m)
+        ev = rel_mean_err(gpu[k][1], sm[k].marginal_var(cfg.sigma_f2))
+        print(f"step {k + 1}: mean {em:.2e} var {ev:.2e}", flush=True)
+        assert em <= 1e-4 and ev <= 1e-4, (k, em, ev)
+
+
 def test_whole_backward_pass_entry_point():
     """cakf_smooth (all steps in one call) against the oracle smoother."""
     import torch
