@@ -162,6 +162,29 @@ def test_truncation_is_eckart_young_optimal_and_conservative():
     assert V is None and np.array_equal(Mq, M)
 
 
+def test_truncated_columns_are_orthogonal_through_predict_and_update():
+    """After a truncation the factor's columns M V_r are mutually orthogonal with the kept
+    eigenvalues as squared norms; the OU prediction scales them by a and the update appends
+    columns, so the Gram of the next untruncated factor begins with the block a^2 diag(lam)
+    (the block a truncation may take as known instead of recomputing it)."""
+    model, steps = tiny_problem(seed=23, T=4, m=8)
+    recs = run_filter(model, steps, 3, 4, policy="cg")
+    checked = 0
+    for prev, cur in zip(recs, recs[1:]):
+        r = prev.M_plus.shape[1]
+        if prev.M.shape[1] <= r:
+            continue                                   # no truncation at this step
+        lam = np.sort(np.linalg.eigvalsh(prev.M.T @ prev.M))[::-1][:r]
+        G = prev.M_plus.T @ prev.M_plus
+        np.testing.assert_allclose(G, np.diag(lam), rtol=1e-10, atol=1e-12 * lam[0])
+        np.testing.assert_allclose(cur.M_pred, model.a * prev.M_plus, rtol=1e-14, atol=0)
+        Gn = cur.M.T @ cur.M
+        np.testing.assert_allclose(Gn[:r, :r], model.a ** 2 * np.diag(lam), rtol=1e-10,
+                                   atol=1e-12 * lam[0])
+        checked += 1
+    assert checked >= 2
+
+
 def test_truncated_filter_covariance_is_psd_and_above_kalman():
     model, steps = tiny_problem(seed=19, T=5, m=8)
     recs = run_filter(model, steps, 3, 4, policy="cg")
