@@ -43,7 +43,7 @@ struct TdShape {
     static int workgroups(int K) { return (K + WAVES * R - 1) / (WAVES * R); }
 };
 using TdSmall = TdShape<10, 8, 5>;     // K <= 640: 40 rows per workgroup
-using TdLarge = TdShape<20, 4, 3>;     // K <= 1280: 12 rows per workgroup
+using TdLarge = TdShape<20, 4, 5>;     // K <= 1280: 20 rows per workgroup (64 at K = 1280)
 
 int tridiag_workgroups(int K) {
     return K <= 64 * TdSmall::kc ? TdSmall::workgroups(K) : TdLarge::workgroups(K);
