@@ -259,7 +259,7 @@ void launch_form_u(const float* part, const float* S, float* U, const ObsDims& d
 // scalars (the same loads, sums in a fixed order).
 struct TailScalars {
     double inv_d, aj, dj;
-    int verdict;      // 0: keep action j; 1: tolerance stop; 2: breakdown; 3: non-finite
+    int outcome;      // 0: keep action j; 1: tolerance stop; 2: breakdown; 3: non-finite
 };
 
 // The step's loads (issued before anything that depends on them, so that a caller can put
@@ -288,13 +288,13 @@ __device__ TailScalars tail_finish(const TailArgs& ta, int j, const TailIn& in) 
     const double cjj = fu - in.tt + ta.noise_var * qjj;
     TailScalars r{0.0, 0.0, 0.0, 0};
     if (j > 0 && ta.resid_tol > 0.0 && qjj <= ta.resid_tol * ta.resid_tol * in.q00) {
-        r.verdict = 1;
+        r.outcome = 1;
         return r;
     }
     const double d2 = cjj - in.l2;
     const bool finite = isfinite(d2) && isfinite(cjj);
     if (!(finite && d2 > ta.pivot_tol * cjj && d2 > 0.0)) {
-        r.verdict = finite ? 2 : 3;
+        r.outcome = finite ? 2 : 3;
         return r;
     }
     r.dj = sqrt(d2);
@@ -324,11 +324,11 @@ __device__ __forceinline__ double tail_beta(const TailArgs& ta, const TailScalar
 // alpha_j and beta_j (into beta_out).
 __device__ void tail_store(const TailArgs& ta, const TailScalars& ts, int j, LoopState* ls) {
     const int tid = threadIdx.x, ld = ta.imax, J = j + 1;
-    if (ts.verdict != 0) {
+    if (ts.outcome != 0) {
         if (tid == 0) {
             ls->stop = 1;
-            if (ts.verdict >= 2) ls->dropped += 1;
-            if (ts.verdict == 3) ls->nonfinite += 1;
+            if (ts.outcome >= 2) ls->dropped += 1;
+            if (ts.outcome == 3) ls->nonfinite += 1;
         }
         return;
     }
@@ -733,7 +733,7 @@ void launch_tail(const ObsDims& d, int jfirst, double noise_var, double resid_to
 //     u_l^T s_jt (l < jt),  s_l^T s_jt (l <= jt),  r0^T s_jt,
 // laid out as [u^T s (jt) | s^T s (jt + 1) | r0^T s] in cpart[block * gs + pos].
 // With tail (jt >= 1) the launch first finishes the Cholesky step of action j = jt - 1
-// (tail_scalars in every wave, tail_store in block 0), and stops on its verdict.
+// (tail_scalars in every wave, tail_store in block 0), and stops on its outcome.
 // RESID, with j = jt - 1: s_jt = r0 - Ghat S beta = r0 - (U - Mo T + noise_var S) beta,
 // the residual after jt actions, stored unnormalised in S[:, jt]; V[:, j] = Mo t_j (the
 // low-rank part kept per row, V = Mo T) and the per-block partial sums of Mo^T s_jt
@@ -820,7 +820,7 @@ __global__ __launch_bounds__(256) void k_next_action(const float* __restrict__ U
     if (tail) {
         ts = tail_finish(ta, j, tin);
         if (blockIdx.x == 0) tail_store(ta, ts, j, ls);
-        if (ts.verdict != 0) return;
+        if (ts.outcome != 0) return;
     }
     // beta_j = beta_{j-1} + alpha_j (row j of L^{-1}), as in tail_beta
 #pragma unroll
